@@ -1,0 +1,29 @@
+"""Build the FP64 CPU oracle library (test infrastructure only).
+
+    python oracle/build.py        -> oracle/libvqmc_ref.so
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libvqmc_ref.so")
+
+
+def build(verbose: bool = False) -> str:
+    src = os.path.join(HERE, "vqmc_ref.c")
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+           "-Wextra", "-Wno-unused-parameter", src, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)
+    sys.exit(0)
