@@ -1,0 +1,331 @@
+// engine.hpp -- fused forward pass of the convolutional amplitude on gfx950.
+//
+// The amplitude of Sec. 2.2 (Eq. wcnn) is a stack of periodic 3x3
+// convolutions: a 1 -> C lift followed by n C -> C layers, tanh after each,
+// and log|W_CNN| = sum over channels and sites of the last layer's output.
+//
+// One workgroup evaluates a batch of G configurations at once.  The batch's
+// G*N lattice sites are the rows of one implicit GEMM per layer:
+//   out[row][co] = sum_{tap, ci} act[nb(row, tap)][ci] * W[co][ci][tap],
+// with K = 9*C ordered tap-major (k = tap*C + ci).  Activations live in LDS
+// for the whole pass (one buffer, updated in place: every wave keeps its
+// output tiles in registers until all waves have finished reading the
+// layer's input).  The weights of a layer are staged once per batch in LDS in
+// the exact per-lane fragment order of the matrix instruction, so each
+// K-step reads them with one conflict-free LDS load per lane.
+//
+// Matrix instructions (64-wide wavefronts, 16x16 output tiles):
+//   FP32   v_mfma_f32_16x16x4_f32   A: act[row=lane%16][k=4s+lane/16]
+//   BF16   v_mfma_f32_16x16x32_bf16 A: act[row=lane%16][k=32s+8(lane/16)+j]
+// both with D[row=4(lane/16)+i][col=lane%16], i = 0..3.
+// BF16X3 splits each operand into hi + lo BF16 parts and accumulates
+// hi*hi + hi*lo + lo*hi (three products per K-step) in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vqmc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+enum Prec { P_F32 = 0, P_BF16 = 1, P_X3 = 2 };
+
+__device__ __forceinline__ int wrapL(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  __bf16 h = (__bf16)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mma_bf16(u16x8 a, u16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1): one exponential and one reciprocal;
+// absolute error ~1e-7 over the whole real line (saturates to +-1).
+__device__ __forceinline__ float tanh_f(float x) {
+  const float e = __expf(2.f * x);
+  return 1.f - __fdividef(2.f, e + 1.f);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Parameter offsets in the flat theta vector (layer 0: lift, then C -> C).
+__host__ __device__ inline int64_t layer_offset(int C, int l) {
+  return l == 0 ? 0 : (int64_t)10 * C + (int64_t)(l - 1) * (9 * C * C + C);
+}
+
+template <int C, int PREC, int NW, int TPW>
+struct Engine {
+  static constexpr int NT = (C + 15) / 16;  // 16-wide output tiles per row tile
+  static constexpr bool F32 = PREC == P_F32;
+  static constexpr bool X3 = PREC == P_X3;
+  static constexpr int KSTEP = F32 ? 4 : 32;
+  static constexpr int KS = (9 * C + KSTEP - 1) / KSTEP;
+  static constexpr int LDA = F32 ? C + 1 : C;  // FP32 rows padded by one word
+  static constexpr int FRAG = F32 ? 4 : (X3 ? 32 : 16);
+  static constexpr int NTHR = NW * 64;
+  static constexpr int MAXROWS = NW * TPW * 16;
+  static constexpr int ACT_BYTES =
+      F32 ? MAXROWS * LDA * 4 : MAXROWS * C * 2 * (X3 ? 2 : 1);
+  static constexpr int FRAG_BYTES = KS * NT * 64 * FRAG;
+  static_assert(F32 ? (C % 4 == 0) : (C % 8 == 0), "channel count not supported");
+  static_assert(8 * MAXROWS <= ACT_BYTES, "row sums must fit the activation buffer");
+
+  // BF16 activation planes: 8-element groups XOR-swizzled by the row so that
+  // the 16 rows of a tile spread over the LDS banks.
+  __device__ static __forceinline__ int phys(int row, int c) {
+    if constexpr (C >= 16) return row * C + ((((c >> 3) ^ (row & (C / 8 - 1))) << 3) | (c & 7));
+    else return row * C + c;
+  }
+
+  __device__ static __forceinline__ void store_act(char *act, int row, int c, float h) {
+    if constexpr (F32) {
+      reinterpret_cast<float *>(act)[row * LDA + c] = h;
+    } else {
+      uint16_t *hi = reinterpret_cast<uint16_t *>(act);
+      const uint16_t bh = bf16_rne(h);
+      hi[phys(row, c)] = bh;
+      if constexpr (X3) hi[MAXROWS * C + phys(row, c)] = bf16_rne(h - bf16_f32(bh));
+    }
+  }
+
+  // Weight fragments of a C -> C layer: entry (s, nt, lane) holds
+  // B[k][n] = W[n][ci][tap] for n = 16 nt + lane%16 and k = tap*C + ci from
+  // the lane's K slice of step s (zero outside the layer).  TRANSPOSED uses
+  // B[k][n] = W[ci][n][tap] (k = tap*C + ci): the input-gradient GEMM.
+  template <bool TRANSPOSED = false>
+  __device__ static __forceinline__ float wsel(const float *W, int k, int n) {
+    if (k >= 9 * C || n >= C) return 0.f;
+    const int tap = k / C, ci = k - tap * C;
+    return TRANSPOSED ? W[(ci * C + n) * 9 + tap] : W[(n * C + ci) * 9 + tap];
+  }
+
+  template <bool TRANSPOSED = false>
+  __device__ static __forceinline__ void stage_weights(const float *__restrict__ W, char *frag) {
+    for (int idx = threadIdx.x; idx < KS * NT * 64; idx += NTHR) {
+      const int s = idx / (NT * 64), rem = idx - s * (NT * 64);
+      const int nt = rem >> 6, ln = rem & 63;
+      const int n = nt * 16 + (ln & 15);
+      if constexpr (F32) {
+        reinterpret_cast<float *>(frag)[idx] = wsel<TRANSPOSED>(W, 4 * s + (ln >> 4), n);
+      } else {
+        const int k0 = 32 * s + 8 * (ln >> 4);
+        u16x8 hi, lo;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float w = wsel<TRANSPOSED>(W, k0 + j, n);
+          hi[j] = bf16_rne(w);
+          lo[j] = bf16_rne(w - bf16_f32(hi[j]));
+        }
+        reinterpret_cast<u16x8 *>(frag + (size_t)idx * FRAG)[0] = hi;
+        if constexpr (X3) reinterpret_cast<u16x8 *>(frag + (size_t)idx * FRAG)[1] = lo;
+      }
+    }
+  }
+
+  // Lift layer: h_1[row][co] = tanh(b0[co] + sum_tap W0[co][tap] s[nb(row,tap)]).
+  __device__ static __forceinline__ void lift(const float *__restrict__ theta, const int8_t *sp, int R, int L, int N,
+                              char *act) {
+    const float *W0 = theta;
+    const float *b0 = theta + 9 * C;
+    for (int idx = threadIdx.x; idx < R * C; idx += NTHR) {
+      const int row = idx / C, co = idx - row * C;
+      const int g = row / N, site = row - g * N, y = site / L, x = site - y * L;
+      float z = b0[co];
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int yy = wrapL(y + tap / 3 - 1, L), xx = wrapL(x + tap % 3 - 1, L);
+        z += W0[co * 9 + tap] * (float)sp[g * N + yy * L + xx];
+      }
+      store_act(act, row, co, tanh_f(z));
+    }
+  }
+
+  __device__ static __forceinline__ int nbrow(int pk, int dy, int dx, int L) {
+    return (pk >> 10) + wrapL(((pk >> 5) & 31) + dy, L) * L + wrapL((pk & 31) + dx, L);
+  }
+
+  // K loop of one conv layer over the wave's row tiles; results stay in acc.
+  // FRAG_GLOBAL: fragments read from a packed global array (else from LDS).
+  // SIGN = -1 gathers act[row - d(tap)] (input-gradient direction).
+  template <bool FRAG_GLOBAL, int SIGN>
+  __device__ static __forceinline__ void kloop(const char *act, const char *frag, int R, int L,
+                                               int N, f32x4 (&acc)[TPW][NT]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // per tile: the lane's row packed as (g*N) << 10 | y << 5 | x
+    int pk[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      int r = (wave + i * NW) * 16 + (lane & 15);
+      r = r < R ? r : R - 1;
+      const int g = r / N, site = r - g * N, y = site / L;
+      pk[i] = ((g * N) << 10) | (y << 5) | (site - y * L);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    if constexpr (F32) {
+      const float *actf = reinterpret_cast<const float *>(act);
+      const float *fragf = reinterpret_cast<const float *>(frag);
+      for (int tap = 0; tap < 9; ++tap) {
+        const int dy = SIGN * (tap / 3 - 1), dx = SIGN * (tap % 3 - 1);
+        int nbo[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+          nbo[i] = nbrow(pk[i], dy, dx, L) * LDA + (lane >> 4);
+#pragma unroll 2
+        for (int c4 = 0; c4 < C / 4; ++c4) {
+          const int s = tap * (C / 4) + c4;
+          float b[NT];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64 + lane];
+          // every tile slot runs (rows past R are clamped copies whose
+          // results are never stored): no branch between the loads and the
+          // matrix instructions
+          float a[TPW];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i) a[i] = actf[nbo[i] + c4 * 4];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a[i], b[nt], acc[i][nt]);
+        }
+      }
+    } else {
+      const uint16_t *hi = reinterpret_cast<const uint16_t *>(act);
+      for (int s = 0; s < KS; ++s) {
+        u16x8 bh[NT], bl[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag + (size_t)((s * NT + nt) * 64 + lane) * FRAG);
+          bh[nt] = f[0];
+          if constexpr (X3) bl[nt] = f[1];
+        }
+        const int k0 = 32 * s + 8 * (lane >> 4);
+        const bool kv = k0 < 9 * C;
+        const int tap = kv ? k0 / C : 0, ci0 = kv ? k0 - tap * C : 0;
+        const int dy = SIGN * (tap / 3 - 1), dx = SIGN * (tap % 3 - 1);
+        // lanes whose K slice lies past 9C read row 0 and multiply zero weights
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int nb = kv ? nbrow(pk[i], dy, dx, L) : 0;
+          const u16x8 ah = *reinterpret_cast<const u16x8 *>(hi + phys(nb, ci0));
+          u16x8 al;
+          if constexpr (X3) al = *reinterpret_cast<const u16x8 *>(hi + MAXROWS * C + phys(nb, ci0));
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[i][nt] = mma_bf16(ah, bh[nt], acc[i][nt]);
+            if constexpr (X3) {
+              acc[i][nt] = mma_bf16(ah, bl[nt], acc[i][nt]);
+              acc[i][nt] = mma_bf16(al, bh[nt], acc[i][nt]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // Writes tanh(acc + bias) of the wave's tiles into the activation buffer
+  // (and, when scratch != nullptr, into scratch[row][co] in global memory).
+  __device__ static __forceinline__ void write_tiles(const f32x4 (&acc)[TPW][NT], const float *bias,
+                                                     int R, char *act, float *scratch) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + (lane & 15);
+      const float bv = co < C ? bias[co] : 0.f;
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int T = wave + i * NW;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = T * 16 + (lane >> 4) * 4 + j;
+          if (row < R && co < C) {
+            const float h = tanh_f(acc[i][nt][j] + bv);
+            store_act(act, row, co, h);
+            if (scratch) scratch[row * C + co] = h;
+          }
+        }
+      }
+    }
+  }
+
+  // Row sums of tanh(acc + bias) over channels, in FP64, into rowsum[row].
+  __device__ static __forceinline__ void head_rows(const f32x4 (&acc)[TPW][NT], const float *bias,
+                                                   int R, double *rowsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float bv[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + (lane & 15);
+      bv[nt] = co < C ? bias[co] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int T = wave + i * NW;
+      if (T * 16 < R) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          if (nt * 16 + (lane & 15) < C) v += (double)tanh_f(acc[i][nt][j] + bv[nt]);
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        const int row = T * 16 + (lane >> 4) * 4 + j;
+        if ((lane & 15) == 0 && row < R) rowsum[row] = v;
+      }
+      }
+    }
+  }
+
+  // Full forward pass of G configurations sp[G][N] (LDS) -> lp[G] (LDS,
+  // FP64).  smem_act / smem_frag are this engine's LDS regions.  Begins and
+  // ends with the block synchronised.
+  __device__ static __forceinline__ void forward(const float *__restrict__ theta, int n_layers, const int8_t *sp,
+                                 int G, int L, int N, char *smem_act, char *smem_frag, double *lp) {
+    const int R = G * N;
+    lift(theta, sp, R, L, N, smem_act);
+    stage_weights(theta + layer_offset(C, 1), smem_frag);
+    __syncthreads();
+    for (int l = 1; l <= n_layers; ++l) {
+      f32x4 acc[TPW][NT];
+      kloop<false, 1>(smem_act, smem_frag, R, L, N, acc);
+      __syncthreads();
+      const float *bias = theta + layer_offset(C, l) + 9 * C * C;
+      if (l < n_layers) {
+        write_tiles(acc, bias, R, smem_act, nullptr);
+        stage_weights(theta + layer_offset(C, l + 1), smem_frag);
+      } else {
+        head_rows(acc, bias, R, reinterpret_cast<double *>(smem_act));
+      }
+      __syncthreads();
+    }
+    const double *rowsum = reinterpret_cast<const double *>(smem_act);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int g = wave; g < G; g += NW) {
+      double p = 0.0;
+      for (int r = lane; r < N; r += 64) p += rowsum[g * N + r];
+      p = wave_sum(p);
+      if (lane == 0) lp[g] = p;
+    }
+    __syncthreads();
+  }
+};
+
+}  // namespace vqmc

@@ -1,0 +1,481 @@
+// forward.hip -- log|psi|, the local-energy generator and the Metropolis
+// exchange sampler, all built on the fused conv engine (engine.hpp).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "engine.hpp"
+
+namespace vqmc {
+
+// ---------------------------------------------------------------- helpers
+
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *tmp) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += tmp[w];
+  __syncthreads();
+  return t;
+}
+
+template <int NW>
+__device__ __forceinline__ int block_isum(int v, int *tmp) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += tmp[w];
+  __syncthreads();
+  return t;
+}
+
+// Exclusive prefix sum over the block (thread order); *total gets the sum.
+template <int NW>
+__device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    base += (w < wave) ? tmp[w] : 0;
+    tot += tmp[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// Bond k of the 4N bonds (Sec. 3.1): kind k / N = 0 right (J1), 1 below
+// (J1), 2 lower-right (J2), 3 lower-left (J2) neighbour of site k % N.
+__device__ __forceinline__ void decode_bond(int k, int L, int N, int &i, int &j, int &kind) {
+  kind = k / N;
+  const int site = k - kind * N, y = site / L, x = site - y * L;
+  i = site;
+  const int yd = wrapL(y + (kind > 0 ? 1 : 0), L);
+  const int xd = wrapL(x + (kind == 0 || kind == 2 ? 1 : (kind == 3 ? -1 : 0)), L);
+  j = yd * L + xd;
+}
+
+// Philox4x32-10 block function (Salmon et al., SC'11): ten rounds, each two
+// 32x32 -> 64-bit products, the round key bumped by the Weyl constants.
+__device__ __forceinline__ void philox(uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+// ------------------------------------------------------------- log |psi|
+
+template <int C, int PREC, int NW, int TPW>
+__global__ __launch_bounds__(NW * 64) void logpsi_kernel(const float *__restrict__ theta,
+                                                         const int8_t *__restrict__ spins, int B,
+                                                         int L, int n_layers, int marshall, int G,
+                                                         double *__restrict__ out,
+                                                         int8_t *__restrict__ sign) {
+  using E = Engine<C, PREC, NW, TPW>;
+  __shared__ __align__(16) char s_act[E::ACT_BYTES];
+  __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
+  __shared__ int8_t s_sp[E::MAXROWS];
+  __shared__ double s_lp[64];
+  const int N = L * L;
+  for (int base = blockIdx.x * G; base < B; base += gridDim.x * G) {
+    const int Gb = min(G, B - base);
+    for (int idx = threadIdx.x; idx < Gb * N; idx += E::NTHR) s_sp[idx] = spins[(size_t)base * N + idx];
+    __syncthreads();
+    E::forward(theta, n_layers, s_sp, Gb, L, N, s_act, s_frag, s_lp);
+    for (int g = threadIdx.x; g < Gb; g += E::NTHR) {
+      out[base + g] = s_lp[g];
+      if (sign) {
+        int up = 0;
+        for (int i = 0; i < N; ++i) {
+          const int y = i / L, x = i - y * L;
+          up += (((x + y) & 1) == 0 && s_sp[g * N + i] > 0);
+        }
+        sign[base + g] = (marshall && (up & 1)) ? -1 : 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- local energy
+
+// One workgroup per sample.  The 4N bonds are scanned in parallel for the
+// diagonal term and the ordered list of antiparallel bonds; then the sample
+// itself and all its exchanged configurations s' are evaluated by the fused
+// engine in batches of G, and the off-diagonal terms J/2 mu exp(dlog) are
+// accumulated in FP64 in bond order.
+template <int C, int PREC, int NW, int TPW>
+__global__ __launch_bounds__(NW * 64) void eloc_kernel(const float *__restrict__ theta,
+                                                       const int8_t *__restrict__ spins, int B, int L,
+                                                       int n_layers, double J1, double J2,
+                                                       int marshall, int G,
+                                                       double *__restrict__ e_loc,
+                                                       int32_t *__restrict__ flags) {
+  using E = Engine<C, PREC, NW, TPW>;
+  constexpr int MR = E::MAXROWS;
+  __shared__ __align__(16) char s_act[E::ACT_BYTES];
+  __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
+  __shared__ int8_t s_sp[MR];
+  __shared__ int8_t s_sig[MR];
+  __shared__ int16_t s_bonds[4 * MR];
+  __shared__ double s_lp[64];
+  __shared__ double s_terms[64];
+  __shared__ double s_red[NW];
+  __shared__ int s_ired[NW];
+  const int tid = threadIdx.x;
+  const int N = L * L, NB = 4 * N;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const int8_t *s = spins + (size_t)b * N;
+    int sz = 0, bad = 0;
+    for (int i = tid; i < N; i += E::NTHR) {
+      const int8_t v = s[i];
+      s_sig[i] = v;
+      sz += v;
+      bad += (v != 1 && v != -1);
+    }
+    sz = block_isum<NW>(sz, s_ired);
+    bad = block_isum<NW>(bad, s_ired);
+    // bond scan: contiguous chunks per thread keep the list in bond order
+    const int chunk = (NB + E::NTHR - 1) / E::NTHR;
+    const int k0 = tid * chunk, k1 = min(k0 + chunk, NB);
+    double dsum = 0.0;
+    int cnt = 0;
+    for (int k = k0; k < k1; ++k) {
+      int i, j, kind;
+      decode_bond(k, L, N, i, j, kind);
+      const int si = s_sig[i], sj = s_sig[j];
+      dsum += 0.25 * (kind < 2 ? J1 : J2) * (double)(si * sj);
+      cnt += (si != sj);
+    }
+    int total;
+    int off = block_excl_scan<NW>(cnt, s_ired, &total);
+    for (int k = k0; k < k1; ++k) {
+      int i, j, kind;
+      decode_bond(k, L, N, i, j, kind);
+      if (s_sig[i] != s_sig[j]) s_bonds[off++] = (int16_t)k;
+    }
+    const double diag = block_sum<NW>(dsum, s_red);
+    const int nconf = 1 + total;
+    double lp0 = 0.0, eacc = diag;
+    for (int q0 = 0; q0 < nconf; q0 += G) {
+      const int Gb = min(G, nconf - q0);
+      for (int idx = tid; idx < Gb * N; idx += E::NTHR) {
+        const int g = idx / N, i = idx - g * N, q = q0 + g;
+        int8_t v = s_sig[i];
+        if (q > 0) {
+          int bi, bj, kind;
+          decode_bond(s_bonds[q - 1], L, N, bi, bj, kind);
+          if (i == bi) v = s_sig[bj];
+          if (i == bj) v = s_sig[bi];
+        }
+        s_sp[idx] = v;
+      }
+      __syncthreads();
+      E::forward(theta, n_layers, s_sp, Gb, L, N, s_act, s_frag, s_lp);
+      if (q0 == 0) lp0 = s_lp[0];
+      for (int g = tid; g < Gb; g += E::NTHR) {
+        const int q = q0 + g;
+        double t = 0.0;
+        if (q > 0) {
+          const int kind = s_bonds[q - 1] / N;
+          const double J = kind < 2 ? J1 : J2;
+          const double mu = (marshall && kind < 2) ? -1.0 : 1.0;
+          t = 0.5 * J * mu * exp(s_lp[g] - lp0);
+        }
+        s_terms[g] = t;
+      }
+      __syncthreads();
+      if (tid == 0)
+        for (int g = 0; g < Gb; ++g) eacc += s_terms[g];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      e_loc[b] = eacc;
+      if (flags) flags[b] = ((!isfinite(eacc) || !isfinite(lp0)) ? 1 : 0) | (sz != 0 ? 2 : 0) | (bad ? 4 : 0);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- sampler
+
+// One chain per workgroup (a single wavefront for small lattices).  Every
+// thread computes the same Philox words and reads the same LDS state, so all
+// control flow below is uniform across the workgroup.
+template <int C, int PREC, int NW, int TPW>
+__global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict__ theta,
+                                                         int8_t *__restrict__ spins, int B, int L,
+                                                         int n_layers, int n_sweeps, uint64_t seed,
+                                                         uint64_t counter_base, int proposal,
+                                                         double *__restrict__ log_psi,
+                                                         int32_t *__restrict__ n_acc) {
+  using E = Engine<C, PREC, NW, TPW>;
+  __shared__ __align__(16) char s_act[E::ACT_BYTES];
+  __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
+  __shared__ int8_t s_sp[E::MAXROWS];
+  __shared__ double s_lp[64];
+  __shared__ int s_ired[NW];
+  __shared__ int s_pick[2];
+  const int tid = threadIdx.x;
+  const int N = L * L;
+  const int b = blockIdx.x;
+  int8_t *s = spins + (size_t)b * N;
+  for (int i = tid; i < N; i += E::NTHR) s_sp[i] = s[i];
+  __syncthreads();
+  E::forward(theta, n_layers, s_sp, 1, L, N, s_act, s_frag, s_lp);
+  double lp = s_lp[0];
+  int acc = 0;
+  const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+  const int chunk = (2 * N + E::NTHR - 1) / E::NTHR;
+  const int k0 = tid * chunk, k1 = min(k0 + chunk, 2 * N);
+  const int64_t steps = (int64_t)n_sweeps * N;
+  for (int64_t t = 0; t < steps; ++t) {
+    const uint64_t tt = counter_base + (uint64_t)t;
+    uint32_t c0 = (uint32_t)tt, c1 = (uint32_t)(tt >> 32), c2 = (uint32_t)b, c3 = 0u;
+    philox(c0, c1, c2, c3, key0, key1);
+    int i = 0, j = 0, nap = 0;
+    if (proposal == 0) {
+      int kind;
+      const int k = (int)(((uint64_t)c0 * (uint64_t)(2 * N)) >> 32);
+      decode_bond(k, L, N, i, j, kind);
+      if (s_sp[i] == s_sp[j]) continue;  // parallel pair: rejected move
+    } else {
+      int cnt = 0;
+      for (int k = k0; k < k1; ++k) {
+        int a, c, kind;
+        decode_bond(k, L, N, a, c, kind);
+        cnt += (s_sp[a] != s_sp[c]);
+      }
+      int off = block_excl_scan<NW>(cnt, s_ired, &nap);
+      if (nap == 0) continue;
+      const int pick = (int)(((uint64_t)c0 * (uint64_t)nap) >> 32);
+      if (pick >= off && pick < off + cnt) {
+        int seen = off;
+        for (int k = k0; k < k1; ++k) {
+          int a, c, kind;
+          decode_bond(k, L, N, a, c, kind);
+          if (s_sp[a] != s_sp[c]) {
+            if (seen == pick) {
+              s_pick[0] = a;
+              s_pick[1] = c;
+            }
+            ++seen;
+          }
+        }
+      }
+      __syncthreads();
+      i = s_pick[0];
+      j = s_pick[1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int8_t v = s_sp[i];
+      s_sp[i] = s_sp[j];
+      s_sp[j] = v;
+    }
+    __syncthreads();
+    E::forward(theta, n_layers, s_sp, 1, L, N, s_act, s_frag, s_lp);
+    const double lpn = s_lp[0];
+    double hast = 0.0;
+    if (proposal == 1) {
+      int cnt = 0;
+      for (int k = k0; k < k1; ++k) {
+        int a, c, kind;
+        decode_bond(k, L, N, a, c, kind);
+        cnt += (s_sp[a] != s_sp[c]);
+      }
+      const int napn = block_isum<NW>(cnt, s_ired);
+      hast = log((double)nap) - log((double)napn);
+    }
+    const double r = ((double)c1 + 0.5) * (1.0 / 4294967296.0);
+    if (2.0 * (lpn - lp) + hast - log(r) >= 0.0) {
+      lp = lpn;
+      ++acc;
+    } else {
+      if (tid == 0) {
+        const int8_t v = s_sp[i];
+        s_sp[i] = s_sp[j];
+        s_sp[j] = v;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < N; i += E::NTHR) s[i] = s_sp[i];
+  if (tid == 0) {
+    if (log_psi) log_psi[b] = lp;
+    if (n_acc) n_acc[b] = acc;
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+
+template <int C>
+struct Inst {
+  static constexpr int NW = 4;
+  static constexpr int TPW = (C == 32) ? 9 : 16;  // rows per block: 576 / 1024
+  static constexpr int SNW = 1;                   // sampler, small lattices
+  static constexpr int STPW = 9;                  // 144 rows
+};
+
+enum Kind { K_LOGPSI, K_ELOC, K_SAMPLE };
+
+struct FwdArgs {
+  const float *theta;
+  const int8_t *spins_in;
+  int8_t *spins_io;
+  int B, L, n_layers, marshall;
+  double J1, J2;
+  double *out_d;
+  int8_t *out_sign;
+  int32_t *out_i;
+  int n_sweeps, proposal;
+  uint64_t seed, counter_base;
+  hipStream_t stream;
+};
+
+template <int C, int PREC>
+static vqmc_status launch(Kind kind, const FwdArgs &a) {
+  using I = Inst<C>;
+  const int N = a.L * a.L;
+  if (kind == K_SAMPLE) {
+    if (a.B == 0 || a.n_sweeps < 0) return VQMC_OK;
+    if (N <= Engine<C, PREC, I::SNW, I::STPW>::MAXROWS) {
+      sample_kernel<C, PREC, I::SNW, I::STPW><<<a.B, I::SNW * 64, 0, a.stream>>>(
+          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal,
+          a.out_d, a.out_i);
+    } else {
+      sample_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
+          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal,
+          a.out_d, a.out_i);
+    }
+    VQMC_LAUNCH_CHECK();
+    return VQMC_OK;
+  }
+  using E = Engine<C, PREC, I::NW, I::TPW>;
+  if (N > E::MAXROWS) return VQMC_ERR_SHAPE;
+  int G = E::MAXROWS / N;
+  G = G > 64 ? 64 : G;
+  if (a.B == 0) return VQMC_OK;
+  if (kind == K_LOGPSI) {
+    const int grid = (a.B + G - 1) / G;
+    logpsi_kernel<C, PREC, I::NW, I::TPW><<<grid, I::NW * 64, 0, a.stream>>>(
+        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.marshall, G, a.out_d, a.out_sign);
+  } else {
+    eloc_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
+        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i);
+  }
+  VQMC_LAUNCH_CHECK();
+  return VQMC_OK;
+}
+
+static vqmc_status dispatch(Kind kind, int C, int prec, const FwdArgs &a) {
+  switch (C) {
+    case 4: return launch<4, P_F32>(kind, a);
+    case 8:
+      return prec == P_F32 ? launch<8, P_F32>(kind, a)
+                           : prec == P_BF16 ? launch<8, P_BF16>(kind, a) : launch<8, P_X3>(kind, a);
+    case 16:
+      return prec == P_F32 ? launch<16, P_F32>(kind, a)
+                           : prec == P_BF16 ? launch<16, P_BF16>(kind, a) : launch<16, P_X3>(kind, a);
+    case 32:
+      return prec == P_F32 ? launch<32, P_F32>(kind, a)
+                           : prec == P_BF16 ? launch<32, P_BF16>(kind, a) : launch<32, P_X3>(kind, a);
+    default: return VQMC_ERR_ARG;
+  }
+}
+
+}  // namespace vqmc
+
+using namespace vqmc;
+
+extern "C" vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta, const int8_t *spins,
+                                    int32_t B, double *log_abs_psi, int8_t *sign,
+                                    hipStream_t stream) {
+  if (!model_valid(m)) return VQMC_ERR_ARG;
+  if (B < 0) return VQMC_ERR_SHAPE;
+  if (B > 0 && (!theta || !spins || !log_abs_psi)) return VQMC_ERR_ARG;
+  FwdArgs a{};
+  a.theta = theta;
+  a.spins_in = spins;
+  a.B = B;
+  a.L = m->L;
+  a.n_layers = m->n_layers;
+  a.marshall = m->marshall;
+  a.out_d = log_abs_psi;
+  a.out_sign = sign;
+  a.stream = stream;
+  return dispatch(K_LOGPSI, m->channels, m->conv_prec, a);
+}
+
+extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
+                                         const int8_t *spins, int32_t B, double *e_loc,
+                                         int32_t *chain_flags, hipStream_t stream) {
+  if (!model_valid(m)) return VQMC_ERR_ARG;
+  if (B < 0) return VQMC_ERR_SHAPE;
+  if (B > 0 && (!theta || !spins || !e_loc)) return VQMC_ERR_ARG;
+  FwdArgs a{};
+  a.theta = theta;
+  a.spins_in = spins;
+  a.B = B;
+  a.L = m->L;
+  a.n_layers = m->n_layers;
+  a.marshall = m->marshall;
+  a.J1 = m->J1;
+  a.J2 = m->J2;
+  a.out_d = e_loc;
+  a.out_i = chain_flags;
+  a.stream = stream;
+  return dispatch(K_ELOC, m->channels, m->conv_prec, a);
+}
+
+extern "C" vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8_t *spins,
+                                   double *log_psi, int32_t B, int32_t n_sweeps, uint64_t seed,
+                                   uint64_t counter_base, int32_t proposal, int32_t *n_accepted,
+                                   hipStream_t stream) {
+  if (!model_valid(m)) return VQMC_ERR_ARG;
+  if (B < 0 || n_sweeps < 0) return VQMC_ERR_SHAPE;
+  if (proposal != 0 && proposal != 1) return VQMC_ERR_ARG;
+  if (B > 0 && (!theta || !spins)) return VQMC_ERR_ARG;
+  FwdArgs a{};
+  a.theta = theta;
+  a.spins_io = spins;
+  a.B = B;
+  a.L = m->L;
+  a.n_layers = m->n_layers;
+  a.marshall = m->marshall;
+  a.out_d = log_psi;
+  a.out_i = n_accepted;
+  a.n_sweeps = n_sweeps;
+  a.proposal = proposal;
+  a.seed = seed;
+  a.counter_base = counter_base;
+  a.stream = stream;
+  return dispatch(K_SAMPLE, m->channels, m->conv_prec, a);
+}

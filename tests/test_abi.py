@@ -1,0 +1,88 @@
+"""The C ABI on the CPU: libvqmc.so loads, exports every entry point that
+include/vqmc.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vqmc.h")
+
+V = pytest.importorskip("paper_2108_13830_amd.vqmc")
+
+if not os.path.exists(V.LIB_PATH):
+    pytest.skip("libvqmc.so not built", allow_module_level=True)
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vqmc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert len(names) == 9
+    lib = ct.CDLL(V.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows every one of them, with the same names
+    assert sorted(n for n, _, _ in V.SIGNATURES) == names
+
+
+def test_num_params_and_model_validation():
+    assert V.num_params(V.Model(4, 4, 2)) == 336
+    assert V.num_params(V.Model(10, 16, 6)) == 14080
+    assert V.num_params(V.Model(24, 32, 8)) == 74304
+    for bad in (V.Model(5, 4, 2), V.Model(26, 4, 2), V.Model(4, 12, 2), V.Model(4, 4, 0),
+                V.Model(4, 4, 2, prec=V.PREC_BF16), V.Model(4, 8, 2, prec=7), V.Model(4, 8, 2, marshall=2)):
+        assert V.num_params(bad) == -1
+
+
+def test_status_strings():
+    lib = V.lib()
+    for code in range(7):
+        assert lib.vqmc_status_string(code)
+    assert lib.vqmc_status_string(99) == b"unknown status"
+
+
+def test_argument_errors_need_no_gpu():
+    lib = V.lib()
+    bad = V.Model(5, 4, 2).c()
+    good = V.Model(4, 4, 2).c()
+    nul = ct.c_void_p(0)
+    assert lib.vqmc_log_psi(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
+    assert lib.vqmc_local_energy(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
+    assert lib.vqmc_log_psi(ct.byref(good), nul, nul, -1, nul, nul, nul) == 2
+    assert lib.vqmc_log_psi(ct.byref(good), nul, nul, 3, nul, nul, nul) == 1
+    # B = 0 is a valid empty call: nothing is launched
+    assert lib.vqmc_log_psi(ct.byref(good), nul, nul, 0, nul, nul, nul) == 0
+    assert lib.vqmc_local_energy(ct.byref(good), nul, nul, 0, nul, nul, nul) == 0
+    assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 2, 1, 0, 0, 5, nul, nul) == 1
+    assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 0, 1, 0, 0, 0, nul, nul) == 0
+    n = ct.c_size_t(0)
+    assert lib.vqmc_log_derivs_workspace(ct.byref(good), 16, ct.byref(n)) == 0 and n.value > 0
+    assert lib.vqmc_log_derivs(ct.byref(good), nul, nul, 16, nul, 10, nul, 0, nul) == 2  # ldO < P
+    assert lib.vqmc_log_derivs(ct.byref(good), nul, nul, 16, ct.c_void_p(8), 336, ct.c_void_p(8),
+                               0, nul) in (1, 4)
+
+
+def test_sr_argument_errors_and_workspace():
+    lib = V.lib()
+    n = ct.c_size_t(0)
+    ok = V.SrOpts().c()
+    assert lib.vqmc_sr_workspace(4096, 14080, ct.byref(ok), ct.byref(n)) == 0
+    assert n.value >= 14080 * 14080 * 8  # the explicit S matrix
+    cg = V.SrOpts(method=V.SR_CG).c()
+    assert lib.vqmc_sr_workspace(16384, 74304, ct.byref(cg), ct.byref(n)) == 0
+    assert n.value < 74304 * 74304 * 8 // 100  # matrix-free
+    bad = V.SrOpts(eps=0.0).c()
+    assert lib.vqmc_sr_workspace(10, 10, ct.byref(bad), ct.byref(n)) == 1
+    assert lib.vqmc_sr_workspace(1, 10, ct.byref(ok), ct.byref(n)) == 2
+    nul = ct.c_void_p(0)
+    assert lib.vqmc_sr_solve(nul, 10, nul, 10, 10, ct.byref(ok), nul, nul, nul, 0, None, nul) == 1
+    assert lib.vqmc_sr_solve(ct.c_void_p(8), 5, ct.c_void_p(8), 10, 10, ct.byref(ok), ct.c_void_p(8),
+                             nul, nul, 0, None, nul) == 2
+    assert lib.vqmc_sr_solve(ct.c_void_p(8), 10, ct.c_void_p(8), 10, 10, ct.byref(ok), ct.c_void_p(8),
+                             nul, nul, 0, None, nul) == 4

@@ -1,0 +1,257 @@
+"""GPU parity of log|psi|, the local energy and the sampler against the FP64
+oracle, through the C ABI (libvqmc.so).  Inputs are the seeded generators of
+vqmc_inputs; every oracle value is computed here or stored by
+tests/golden/make_golden.py (oracle only)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import R, V, models, to_dev, host, announce
+from vqmc_inputs import init_theta, neel, uniform_sz0, ferro_like_sz0
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_large.json")
+
+# (L, C, n, B): B ragged against the batch sizes of the kernels
+SHAPES = [(4, 4, 2, 37), (6, 8, 2, 29), (10, 16, 6, 23), (16, 32, 8, 9), (24, 32, 8, 3)]
+# absolute log|psi| tolerance per precision (FP32 accumulation everywhere)
+LP_TOL = {V.PREC_FP32: 2e-4, V.PREC_BF16X3: 5e-3, V.PREC_BF16: 5.0}
+
+
+@pytest.mark.parametrize("L,C,n,B", SHAPES)
+@pytest.mark.parametrize("prec", [V.PREC_FP32, V.PREC_BF16X3, V.PREC_BF16])
+def test_log_psi_parity(L, C, n, B, prec):
+    if prec != V.PREC_FP32 and C % 8:
+        pytest.skip("BF16 forms need C % 8 == 0")
+    gm, rm = models(L, C, n, prec)
+    th = init_theta(C, n, seed=0)
+    s = uniform_sz0(L, B, seed=1)
+    ref, rsg = R.log_psi(rm, th, s)
+    announce("log_psi", L, C, n, B, prec)
+    sign = torch.empty(B, dtype=torch.int8, device="cuda")
+    got = host(V.vqmc_log_psi(gm, to_dev(th), to_dev(s), sign=sign))
+    err = np.abs(got - ref)
+    print("log_psi L=%d prec=%d max|err|=%.3e max|ref|=%.3e" % (L, prec, err.max(), np.abs(ref).max()))
+    assert err.max() <= LP_TOL[prec]
+    assert (host(sign) == rsg).all()
+
+
+def test_log_psi_empty_and_single():
+    gm, rm = models(10, 16, 6)
+    th = to_dev(init_theta(16, 6, seed=0))
+    out = V.vqmc_log_psi(gm, th, torch.empty((0, 100), dtype=torch.int8, device="cuda"))
+    assert out.numel() == 0
+    s = uniform_sz0(10, 1, seed=3)
+    got = host(V.vqmc_log_psi(gm, th, to_dev(s)))
+    assert abs(got[0] - R.log_psi(rm, init_theta(16, 6, seed=0), s)[0][0]) < 1e-4
+
+
+def _eloc_check(L, C, n, prec, s, th, rel_tol_mean, rel_tol_each=None, **kw):
+    gm, rm = models(L, C, n, prec, **kw)
+    ref = R.local_energy(rm, th, s)
+    announce("local_energy", L, C, n, s.shape[0], prec, kw)
+    flags = torch.full((s.shape[0],), -1, dtype=torch.int32, device="cuda")
+    got = host(V.vqmc_local_energy(gm, to_dev(th), to_dev(s), flags=flags))
+    assert (host(flags) == 0).all()
+    rel_mean = abs(got.mean() - ref.mean()) / abs(ref.mean())
+    rel_each = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    print("E_loc L=%d prec=%d  |dE/N| rel=%.3e  max per-sample rel=%.3e" % (L, prec, rel_mean, rel_each.max()))
+    assert rel_mean <= rel_tol_mean
+    if rel_tol_each is not None:
+        assert rel_each.max() <= rel_tol_each
+    return got, ref
+
+
+@pytest.mark.parametrize("L,C,n,B", [(4, 4, 2, 33), (6, 8, 2, 17), (10, 16, 6, 12)])
+def test_local_energy_fp32(L, C, n, B):
+    th = init_theta(C, n, seed=0)
+    _eloc_check(L, C, n, V.PREC_FP32, uniform_sz0(L, B, seed=1), th, 1e-6, 1e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [(V.PREC_BF16X3, 1e-4), (V.PREC_BF16, 1.0)])
+def test_local_energy_bf16_forms_10x10(prec, tol):
+    th = init_theta(16, 6, seed=0)
+    _eloc_check(10, 16, 6, prec, uniform_sz0(10, 12, seed=1), th, tol)
+
+
+def test_local_energy_neel_and_edge_configs():
+    th = init_theta(8, 2, seed=4)
+    s = np.concatenate([neel(6, 1), ferro_like_sz0(6), uniform_sz0(6, 3, seed=9)])
+    _eloc_check(6, 8, 2, V.PREC_FP32, s, th, 1e-6, 1e-5)
+    # couplings and sign rule variants
+    _eloc_check(6, 8, 2, V.PREC_FP32, s, th, 1e-6, 1e-5, J2=0.0)
+    _eloc_check(6, 8, 2, V.PREC_FP32, s, th, 1e-6, 1e-5, marshall=0, J1=0.7, J2=-0.3)
+
+
+def test_local_energy_zero_params_neel():
+    """All parameters zero: E_loc(Neel)/N = -1.25 exactly (closed form)."""
+    for L, C, n in ((4, 4, 2), (10, 16, 6)):
+        gm, _ = models(L, C, n)
+        th = torch.zeros(V.num_params(gm), dtype=torch.float32, device="cuda")
+        got = host(V.vqmc_local_energy(gm, th, to_dev(neel(L, 2))))
+        np.testing.assert_allclose(got / (L * L), -1.25, rtol=0, atol=1e-12)
+
+
+def test_local_energy_flags():
+    gm, rm = models(6, 8, 2)
+    th = init_theta(8, 2, seed=4)
+    s = uniform_sz0(6, 3, seed=2)
+    s[1, np.nonzero(s[1] < 0)[0][0]] = 1      # Sz != 0
+    s[2, 5] = 3                               # not a spin value
+    flags = torch.zeros(3, dtype=torch.int32, device="cuda")
+    V.vqmc_local_energy(gm, to_dev(th), to_dev(s), flags=flags)
+    f = host(flags)
+    _, rf = R.local_energy(rm, th, s, with_flags=True)
+    assert f[0] == 0 and (f[1] & 2) and (f[2] & 4)
+    assert (f == rf).all()
+    # non-finite parameters are flagged
+    bad = th.copy()
+    bad[3] = np.nan
+    V.vqmc_local_energy(gm, to_dev(bad), to_dev(s[:1]), flags=flags[:1])
+    assert host(flags)[0] & 1
+
+
+def test_local_energy_enumeration_identity_4x4():
+    """sum_s |psi|^2 E_loc(s) = <psi|H|psi> with GPU log|psi| and E_loc over all
+    12870 Sz = 0 states (Eq. sum-Es), H built independently by the oracle."""
+    gm, rm = models(4, 4, 2)
+    th = init_theta(4, 2, seed=0)
+    H, states = R.hamiltonian(4, 1.0, 0.5)
+    announce("enumeration 4x4")
+    sd = to_dev(states)
+    sign = torch.empty(states.shape[0], dtype=torch.int8, device="cuda")
+    la = host(V.vqmc_log_psi(gm, to_dev(th), sd, sign=sign))
+    el = host(V.vqmc_local_energy(gm, to_dev(th), sd))
+    w = np.exp(2 * (la - la.max()))
+    lhs = (w * el).sum() / w.sum()
+    rhs = R.exact_energy(H, la, host(sign))
+    assert lhs == pytest.approx(rhs, rel=1e-9)
+    ref_e = R.exact_energy(H, *R.log_psi(rm, th, states))
+    assert lhs == pytest.approx(ref_e, rel=1e-6)
+
+
+def _golden():
+    with open(GOLD) as f:
+        return {c["L"]: c for c in json.load(f)["cases"]}
+
+
+@pytest.mark.parametrize("L", [16, 24])
+@pytest.mark.parametrize("prec", [V.PREC_FP32, V.PREC_BF16X3])
+def test_large_lattices_against_stored_oracle(L, prec):
+    g = _golden()[L]
+    C, n, ns = g["C"], g["n"], g["n_samples"]
+    gm, _ = models(L, C, n, prec)
+    th = to_dev(init_theta(C, n, seed=0))
+    s = uniform_sz0(L, ns, seed=1)
+    announce("large", L, prec)
+    lp = host(V.vqmc_log_psi(gm, th, to_dev(s)))
+    el = host(V.vqmc_local_energy(gm, th, to_dev(s)))
+    ref_lp, ref_el = np.array(g["log_psi"]), np.array(g["e_loc"])
+    print("L=%d prec=%d lp err %.3e  E rel %s" % (L, prec, np.abs(lp - ref_lp).max(),
+                                                np.abs(el - ref_el) / np.abs(ref_el)))
+    assert np.abs(lp - ref_lp).max() <= LP_TOL[prec]
+    assert abs(el.mean() - ref_el.mean()) / abs(ref_el.mean()) <= (1e-6 if prec == 0 else 1e-4)
+
+
+# ---------------------------------------------------------------- sampler
+
+def test_sampler_trajectories_match_oracle_4x4():
+    gm, rm = models(4, 4, 2)
+    th = init_theta(4, 2, seed=0)
+    B = 256
+    s0 = neel(4, B)
+    rs, rla, rna, margin = R.sample(rm, th, s0, n_sweeps=4, seed=2)
+    announce("sampler 4x4")
+    sd = to_dev(s0)
+    lp = torch.empty(B, dtype=torch.float64, device="cuda")
+    na = torch.empty(B, dtype=torch.int32, device="cuda")
+    V.vqmc_sample(gm, to_dev(th), sd, n_sweeps=4, seed=2, log_psi=lp, n_accepted=na)
+    gs, gla, gna = host(sd), host(lp), host(na)
+    assert (gs.sum(axis=1) == 0).all()
+    clear = margin > 1e-3                      # no near-tie decision on the oracle path
+    print("chains compared: %d / %d" % (clear.sum(), B))
+    assert clear.sum() >= 0.9 * B
+    assert (gs[clear] == rs[clear]).all()
+    assert (gna[clear] == rna[clear]).all()
+    np.testing.assert_allclose(gla[clear], rla[clear], atol=1e-4)
+
+
+def test_sampler_hastings_proposal_matches_oracle():
+    gm, rm = models(6, 8, 2)
+    th = init_theta(8, 2, seed=1)
+    B = 64
+    s0 = uniform_sz0(6, B, seed=5)
+    rs, _, rna, margin = R.sample(rm, th, s0, n_sweeps=2, seed=3, proposal=1)
+    sd = to_dev(s0)
+    na = torch.empty(B, dtype=torch.int32, device="cuda")
+    V.vqmc_sample(gm, to_dev(th), sd, n_sweeps=2, seed=3, proposal=1, n_accepted=na)
+    clear = margin > 1e-3
+    assert clear.sum() >= 0.8 * B
+    assert (host(sd)[clear] == rs[clear]).all()
+    assert (host(na)[clear] == rna[clear]).all()
+
+
+def test_sampler_10x10_matches_oracle():
+    gm, rm = models(10, 16, 6)
+    th = init_theta(16, 6, seed=0)
+    B = 48
+    s0 = neel(10, B)
+    rs, _, rna, margin = R.sample(rm, th, s0, n_sweeps=1, seed=7, counter_base=1000)
+    sd = to_dev(s0)
+    na = torch.empty(B, dtype=torch.int32, device="cuda")
+    announce("sampler 10x10")
+    V.vqmc_sample(gm, to_dev(th), sd, n_sweeps=1, seed=7, counter_base=1000, n_accepted=na)
+    clear = margin > 1e-3
+    assert clear.sum() >= 0.8 * B
+    assert (host(sd)[clear] == rs[clear]).all()
+
+
+def test_sampler_reproducible_and_counter_split():
+    gm, _ = models(6, 8, 2, V.PREC_BF16X3)
+    th = to_dev(init_theta(8, 2, seed=0))
+    s0 = to_dev(neel(6, 32))
+    a = s0.clone()
+    V.vqmc_sample(gm, th, a, n_sweeps=3, seed=99)
+    b = s0.clone()
+    V.vqmc_sample(gm, th, b, n_sweeps=3, seed=99)
+    assert torch.equal(a, b)
+    c = s0.clone()
+    V.vqmc_sample(gm, th, c, n_sweeps=1, seed=99)
+    V.vqmc_sample(gm, th, c, n_sweeps=2, seed=99, counter_base=36)
+    assert torch.equal(a, c)
+    assert int(a.to(torch.int32).sum(dim=1).abs().max()) == 0
+
+
+def _stag(states, L):
+    y, x = np.divmod(np.arange(L * L), L)
+    sgn = np.where((x + y) % 2 == 0, 1, -1)
+    return np.abs((states * sgn).sum(axis=1)) // 2
+
+
+def test_sampler_distribution_4x4():
+    """Brute force: GPU chains sample |psi|^2 over the 12870 states."""
+    gm, rm = models(4, 4, 2)
+    th = init_theta(4, 2, seed=0)
+    H, states = R.hamiltonian(4, 1.0, 0.5)
+    la, _ = R.log_psi(rm, th, states)
+    el = R.local_energy(rm, th, states)
+    p = np.exp(2 * (la - la.max()))
+    p /= p.sum()
+    chains = 4096
+    sd = to_dev(neel(4, chains))
+    announce("sampler distribution")
+    V.vqmc_sample(gm, to_dev(th), sd, n_sweeps=80, seed=2024)
+    s = host(sd)
+    ms = _stag(states, 4)
+    hist = np.bincount(_stag(s, 4), minlength=9)[:9]
+    exp = np.array([p[ms == k].sum() for k in range(9)]) * chains
+    keep = exp > 5
+    chi2 = (((hist[keep] - exp[keep]) ** 2) / exp[keep]).sum()
+    assert chi2 < 3 * keep.sum() + 20, (hist, exp)
+    e_s = host(V.vqmc_local_energy(gm, to_dev(th), sd))
+    assert abs(e_s.mean() - (p * el).sum()) < 5 * e_s.std() / math.sqrt(chains)
