@@ -1,0 +1,213 @@
+"""Benchmark of the VQMC + SR hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 10x10|16x16|24x24]
+                    [--conv fp32|bf16|bf16x3] [--sr auto|chol32|chol64|dual|cg]
+
+One step = local energies of B samples (every exchanged configuration
+evaluated), per-sample log-derivatives O_k, and one SR solve
+(S + eps I) delta = F, on inputs resident in GPU memory.  Prints one JSON
+line.  The sampler that produces the 10x10 configurations (1000 sweeps from
+the Neel state) runs before the timed region and is reported separately.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VQMC samples/s (E_loc+O_k+SR step) at 10×10 & 24×24, J2/J1=0.5; BF16 vs FP32"
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "fp64": 78.6}  # TFLOP/s, dense
+HBM_PEAK = 8000.0  # GB/s
+
+
+def f_cfg(L, C, n):
+    """Dense FLOPs of one configuration's forward pass (2 per multiply-add)."""
+    return 2 * L * L * 9 * (C + n * C * C)
+
+
+def antiparallel_counts(spins, L):
+    """Number of antiparallel J1 + J2 bonds per configuration (bench-side
+    bookkeeping for the algorithmic FLOP count)."""
+    s = spins.reshape(-1, L, L).astype(np.int16)
+    c = np.zeros(s.shape[0], np.int64)
+    for dy, dx in ((0, 1), (1, 0), (1, 1), (1, -1)):
+        c += (s != np.roll(s, (-dy, -dx), axis=(1, 2))).sum(axis=(1, 2))
+    return c
+
+
+WORKLOADS = {
+    "10x10": dict(L=10, C=16, n=6, B=4096, spins="sampled", sr="chol32"),
+    "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="cg"),
+    "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="cg"),
+}
+
+
+def sr_opts(V, name):
+    return {
+        "chol32": V.SrOpts(method=V.SR_CHOLESKY, s_prec=0, eps=1e-4),
+        "chol64": V.SrOpts(method=V.SR_CHOLESKY, s_prec=1, eps=1e-4),
+        "dual": V.SrOpts(method=V.SR_DUAL, eps=1e-4),
+        "cg": V.SrOpts(method=V.SR_CG, eps=1e-4, tol=1e-8, max_iter=200),
+    }[name]
+
+
+def cpu_baseline(wl, th, spins, sample):
+    """The FP64 oracle on a bounded sample of the same workload."""
+    import oracle as R
+    m = R.RefModel(wl["L"], wl["C"], wl["n"], 1.0, 0.5, 1)
+    s = spins[:sample]
+    t0 = time.perf_counter()
+    e = R.local_energy(m, th, s)
+    O = R.log_derivs(m, th, s)
+    R.sr_solve(O, e, 1e-4)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sample / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d of the %d configurations: E_loc + O_k + exact SR solve on that "
+                      "subset, FP64 plain loops (%.1f s)" % (sample, len(spins), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="10x10", choices=sorted(WORKLOADS))
+    ap.add_argument("--conv", default="fp32", choices=["fp32", "bf16", "bf16x3"])
+    ap.add_argument("--sr", default=None, choices=["chol32", "chol64", "dual", "cg"])
+    ap.add_argument("--burn-in", type=int, default=1000)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual",
+                    help="extra forms timed on the same inputs (comma list, or 'none')")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2108_13830_amd import vqmc as V
+    from vqmc_inputs import init_theta, neel, uniform_sz0
+
+    wl = dict(WORKLOADS[args.workload])
+    sr_name = args.sr or wl["sr"]
+    L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    th_np = init_theta(C, n, seed=0)
+    th = torch.from_numpy(th_np).to(dev)
+    gm = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_NAMES[args.conv])
+    P = V.num_params(gm)
+
+    # ---- inputs (resident before the timed region)
+    sampler = None
+    if wl["spins"] == "sampled":
+        spins = torch.from_numpy(neel(L, B)).to(dev)
+        acc = torch.empty(B, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        V.vqmc_sample(gm.with_prec("fp32"), th, spins, n_sweeps=args.burn_in, seed=2, n_accepted=acc)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        sampler = {"chains": B, "sweeps": args.burn_in, "seconds": ts,
+                   "proposals_per_s": B * args.burn_in * L * L / ts,
+                   "acceptance": float(acc.sum().item()) / (B * args.burn_in * L * L)}
+    else:
+        spins = torch.from_numpy(uniform_sz0(L, B, seed=1)).to(dev)
+    spins_np = spins.cpu().numpy()
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    O = torch.empty((B, P), dtype=torch.float32, device=dev)
+    ws_o = torch.empty(max(V.log_derivs_workspace(gm, B), 1), dtype=torch.uint8, device=dev)
+    opts = sr_opts(V, sr_name)
+    ws_sr = torch.empty(max(V.sr_workspace(B, P, opts), 1), dtype=torch.uint8, device=dev)
+    delta = torch.empty(P, dtype=torch.float64, device=dev)
+    F = torch.empty(P, dtype=torch.float64, device=dev)
+
+    def run_step(model, o, ws, times=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if times is not None else None
+        if ev:
+            ev[0].record()
+        V.vqmc_local_energy(model, th, spins, out=e)
+        if ev:
+            ev[1].record()
+        V.vqmc_log_derivs(gm.with_prec("fp32"), th, spins, O=O, workspace=ws_o)
+        if ev:
+            ev[2].record()
+        V.vqmc_sr_solve(O, e, o, delta=delta, F=F, workspace=ws, want_info=False)
+        if ev:
+            ev[3].record()
+            times.append(ev)
+
+    def timed(model, o, ws, steps, warmup):
+        for _ in range(warmup):
+            run_step(model, o, ws)
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run_step(model, o, ws, evs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = np.array([[evs[i][j].elapsed_time(evs[i][j + 1]) for j in range(3)] for i in range(steps)])
+        return wall / steps * 1e3, st.mean(axis=0)
+
+    ms, stage = timed(gm, opts, ws_sr, args.steps, args.warmup)
+    value = B / (ms / 1e3)
+
+    # ---- roofline of the dominant kernel (the fused local-energy kernel:
+    # one launch per call, so the call's event time is the kernel's time)
+    nap = antiparallel_counts(spins_np, L)
+    flops_eloc = float((1 + nap).sum()) * f_cfg(L, C, n)
+    t_eloc = stage[0] / 1e3
+    conv_peak = PEAK[args.conv]
+    achieved = flops_eloc / t_eloc / 1e12
+    roof = {"bound": "mfma", "kernel": "eloc_kernel", "achieved": achieved, "peak": conv_peak,
+            "unit": "TFLOP/s", "frac": achieved / conv_peak, "traffic": None,
+            "algorithmic_flops_per_launch": flops_eloc,
+            "executed_mfma_flops_per_launch": flops_eloc * (3 if args.conv == "bf16x3" else 1)}
+
+    out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": args.conv, "data": "synthetic",
+           "config": {"workload": "%s periodic J1-J2 (J2/J1=0.5), C=%d, n=%d, P=%d, B=%d %s configurations; "
+                                  "E_loc + O_k + SR (%s), %s convolutions"
+                                  % (args.workload, C, n, P, B, wl["spins"], sr_name, args.conv),
+                      "L": L, "channels": C, "layers": n, "params": P, "samples": B,
+                      "conv": args.conv, "sr": sr_name},
+           "stage_ms": {"local_energy": stage[0], "log_derivs": stage[1], "sr_solve": stage[2]},
+           "roofline": roof}
+    if sampler:
+        out["sampler"] = sampler
+
+    variants = {}
+    if args.variants != "none":
+        for v in args.variants.split(","):
+            if v in ("bf16", "bf16x3", "fp32") and v != args.conv:
+                vms, vst = timed(gm.with_prec(v), opts, ws_sr, 1, 1)
+                variants["conv_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
+                                         "stage_ms": vst.tolist(),
+                                         "eloc_tflops_algorithmic": flops_eloc / (vst[0] / 1e3) / 1e12}
+            elif v in ("chol32", "chol64", "dual", "cg") and v != sr_name:
+                vo = sr_opts(V, v)
+                vws = torch.empty(max(V.sr_workspace(B, P, vo), 1), dtype=torch.uint8, device=dev)
+                vms, vst = timed(gm, vo, vws, 1, 1)
+                variants["sr_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
+                                       "stage_ms": vst.tolist()}
+                del vws
+    if variants:
+        out["variants"] = variants
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, th_np, spins_np, min(args.cpu_sample, B))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
