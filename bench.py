@@ -33,13 +33,36 @@ def f_cfg(L, C, n):
 
 
 def antiparallel_counts(spins, L):
-    """Number of antiparallel J1 + J2 bonds per configuration (bench-side
-    bookkeeping for the algorithmic FLOP count)."""
+    """Antiparallel bonds per configuration, by bond kind (right, below,
+    lower-right, lower-left): bench-side bookkeeping for FLOP counts."""
     s = spins.reshape(-1, L, L).astype(np.int16)
-    c = np.zeros(s.shape[0], np.int64)
-    for dy, dx in ((0, 1), (1, 0), (1, 1), (1, -1)):
-        c += (s != np.roll(s, (-dy, -dx), axis=(1, 2))).sum(axis=(1, 2))
-    return c
+    return np.stack([(s != np.roll(s, (-dy, -dx), axis=(1, 2))).sum(axis=(1, 2))
+                     for dy, dx in ((0, 1), (1, 0), (1, 1), (1, -1))], axis=1)
+
+
+def eloc_flops(spins, L, C, n, lightcone, conv):
+    """(algorithmic, executed-on-matrix-cores) FLOPs of one local-energy call.
+    Dense: (1 + n_ap) forward passes per sample.  Light cone: one forward
+    pass per sample plus, per exchanged pair and layer, the convolution rows
+    of the pair's neighbourhood at that distance (executed: rows padded to
+    16-row tiles; split-BF16 executes three products)."""
+    nap = antiparallel_counts(spins, L)
+    mult = 3 if conv == "bf16x3" else 1
+    if not lightcone:
+        f = float((1 + nap.sum(axis=1)).sum()) * f_cfg(L, C, n)
+        return f, f * mult
+    per_row = 2 * 9 * C * C
+    alg = np.zeros(4)
+    exe = np.zeros(4)
+    for kind, (ey, ex) in enumerate(((0, 1), (1, 0), (1, 1), (1, 1))):
+        for l in range(1, n + 1):
+            d = l + 1
+            rows = min(ey + 1 + 2 * d, L) * min(ex + 1 + 2 * d, L)
+            alg[kind] += rows * per_row
+            exe[kind] += -(-rows // 16) * 16 * per_row
+    B = spins.shape[0]
+    base = B * f_cfg(L, C, n)
+    return base + float((nap * alg).sum()), base + float((nap * exe).sum()) * mult
 
 
 WORKLOADS = {
@@ -82,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="10x10", choices=sorted(WORKLOADS))
     ap.add_argument("--conv", default="fp32", choices=["fp32", "bf16", "bf16x3"])
     ap.add_argument("--sr", default=None, choices=["chol32", "chol64", "dual", "cg"])
+    ap.add_argument("--eloc", default="auto", choices=["auto", "dense", "lightcone"])
+    ap.add_argument("--samples", type=int, default=None, help="override B")
     ap.add_argument("--burn-in", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -98,13 +123,17 @@ def main():
     from vqmc_inputs import init_theta, neel, uniform_sz0
 
     wl = dict(WORKLOADS[args.workload])
+    if args.samples:
+        wl["B"] = args.samples
     sr_name = args.sr or wl["sr"]
     L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     th_np = init_theta(C, n, seed=0)
     th = torch.from_numpy(th_np).to(dev)
-    gm = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_NAMES[args.conv])
+    eloc_mode = {"auto": V.ELOC_AUTO, "dense": V.ELOC_DENSE, "lightcone": V.ELOC_LIGHTCONE}[args.eloc]
+    gm = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_NAMES[args.conv], eloc_mode)
+    lightcone = V.local_energy_workspace(gm, 1) > 0
     P = V.num_params(gm)
 
     # ---- inputs (resident before the timed region)
@@ -126,6 +155,13 @@ def main():
     e = torch.empty(B, dtype=torch.float64, device=dev)
     O = torch.empty((B, P), dtype=torch.float32, device=dev)
     ws_o = torch.empty(max(V.log_derivs_workspace(gm, B), 1), dtype=torch.uint8, device=dev)
+    ws_e = {}
+
+    def eloc_ws(model):
+        if model not in ws_e:
+            nb = V.local_energy_workspace(model, B)
+            ws_e[model] = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+        return ws_e[model]
     opts = sr_opts(V, sr_name)
     ws_sr = torch.empty(max(V.sr_workspace(B, P, opts), 1), dtype=torch.uint8, device=dev)
     delta = torch.empty(P, dtype=torch.float64, device=dev)
@@ -135,7 +171,7 @@ def main():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if times is not None else None
         if ev:
             ev[0].record()
-        V.vqmc_local_energy(model, th, spins, out=e)
+        V.vqmc_local_energy(model, th, spins, out=e, workspace=eloc_ws(model))
         if ev:
             ev[1].record()
         V.vqmc_log_derivs(gm.with_prec("fp32"), th, spins, O=O, workspace=ws_o)
@@ -164,24 +200,27 @@ def main():
 
     # ---- roofline of the dominant kernel (the fused local-energy kernel:
     # one launch per call, so the call's event time is the kernel's time)
-    nap = antiparallel_counts(spins_np, L)
-    flops_eloc = float((1 + nap).sum()) * f_cfg(L, C, n)
+    flops_eloc, flops_exec = eloc_flops(spins_np, L, C, n, lightcone, args.conv)
+    dense_equiv, _ = eloc_flops(spins_np, L, C, n, False, args.conv)
     t_eloc = stage[0] / 1e3
     conv_peak = PEAK[args.conv]
     achieved = flops_eloc / t_eloc / 1e12
-    roof = {"bound": "mfma", "kernel": "eloc_kernel", "achieved": achieved, "peak": conv_peak,
-            "unit": "TFLOP/s", "frac": achieved / conv_peak, "traffic": None,
-            "algorithmic_flops_per_launch": flops_eloc,
-            "executed_mfma_flops_per_launch": flops_eloc * (3 if args.conv == "bf16x3" else 1)}
+    roof = {"bound": "mfma", "kernel": "eloc_lc_kernel" if lightcone else "eloc_kernel",
+            "achieved": achieved, "peak": conv_peak, "unit": "TFLOP/s", "frac": achieved / conv_peak,
+            "traffic": None, "algorithmic_flops_per_launch": flops_eloc,
+            "executed_mfma_flops_per_launch": flops_exec,
+            "executed_tflops": flops_exec / t_eloc / 1e12,
+            "dense_equivalent_tflops": dense_equiv / t_eloc / 1e12}
 
     out = {"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": args.conv, "data": "synthetic",
            "config": {"workload": "%s periodic J1-J2 (J2/J1=0.5), C=%d, n=%d, P=%d, B=%d %s configurations; "
-                                  "E_loc + O_k + SR (%s), %s convolutions"
-                                  % (args.workload, C, n, P, B, wl["spins"], sr_name, args.conv),
+                                  "E_loc (%s) + O_k + SR (%s), %s convolutions"
+                                  % (args.workload, C, n, P, B, wl["spins"],
+                                     "light cone" if lightcone else "dense", sr_name, args.conv),
                       "L": L, "channels": C, "layers": n, "params": P, "samples": B,
-                      "conv": args.conv, "sr": sr_name},
+                      "conv": args.conv, "sr": sr_name, "eloc": "lightcone" if lightcone else "dense"},
            "stage_ms": {"local_energy": stage[0], "log_derivs": stage[1], "sr_solve": stage[2]},
            "roofline": roof}
     if sampler:
@@ -195,6 +234,15 @@ def main():
                 variants["conv_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
                                          "stage_ms": vst.tolist(),
                                          "eloc_tflops_algorithmic": flops_eloc / (vst[0] / 1e3) / 1e12}
+            elif v in ("dense", "lightcone"):
+                vm = gm.with_eloc(V.ELOC_DENSE if v == "dense" else V.ELOC_LIGHTCONE)
+                if (v == "lightcone") == lightcone:
+                    continue
+                vms, vst = timed(vm, opts, ws_sr, 1, 1)
+                fa, _ = eloc_flops(spins_np, L, C, n, v == "lightcone", args.conv)
+                variants["eloc_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
+                                         "stage_ms": vst.tolist(),
+                                         "eloc_tflops_algorithmic": fa / (vst[0] / 1e3) / 1e12}
             elif v in ("chol32", "chol64", "dual", "cg") and v != sr_name:
                 vo = sr_opts(V, v)
                 vws = torch.empty(max(V.sr_workspace(B, P, vo), 1), dtype=torch.uint8, device=dev)

@@ -55,6 +55,15 @@ typedef enum { VQMC_PREC_FP32 = 0, VQMC_PREC_BF16 = 1, VQMC_PREC_BF16X3 = 2 } vq
 
 typedef enum { VQMC_ACT_TANH = 0 } vqmc_act;
 
+/* How vqmc_local_energy evaluates the exchanged configurations s':
+ *   DENSE     -- the full forward pass of every s' (batched per workgroup);
+ *   LIGHTCONE -- one FP32 forward pass of s per sample, then for every s'
+ *                only the change of the activations inside the growing
+ *                neighbourhood of the exchanged pair (needs channels 16 or
+ *                32 and a workspace);
+ *   AUTO      -- LIGHTCONE when supported and L >= 14, else DENSE. */
+typedef enum { VQMC_ELOC_AUTO = 0, VQMC_ELOC_DENSE = 1, VQMC_ELOC_LIGHTCONE = 2 } vqmc_eloc_mode;
+
 /* The variational state and the Hamiltonian.
  *   L          lattice side, even, 4 <= L <= 24;
  *   channels   C in {4, 8, 16, 32};
@@ -66,12 +75,15 @@ typedef enum { VQMC_ACT_TANH = 0 } vqmc_act;
  *              + J2/4 sum_<<ij>> s_i.s_j;
  *   marshall   1: W = (-1)^{N_up(A)} W_CNN (Sec. 2.2), 0: W = W_CNN;
  *   conv_prec  vqmc_prec of the forward convolutions (log psi, local energy
- *              and sampler).  The log-derivative path always runs FP32. */
+ *              and sampler; with LIGHTCONE, of the convolutions of the
+ *              activation changes).  The log-derivative path always runs FP32;
+ *   eloc_mode  vqmc_eloc_mode. */
 typedef struct {
   int32_t L, channels, n_layers, activation;
   double J1, J2;
   int32_t marshall;
   int32_t conv_prec;
+  int32_t eloc_mode;
 } vqmc_model;
 
 /* Number of parameters P = (9C + C) + n (9C^2 + C); < 0 for an invalid model. */
@@ -113,10 +125,17 @@ vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta,
  * J1 and +1 for J2 bonds when marshall = 1).  Every s' of a sample is built
  * on chip and evaluated in the same launch.  e_loc: dev double [B].
  * chain_flags (dev int32 [B], nullable): bit 1 non-finite log psi or E_s,
- * bit 2 Sz != 0, bit 4 a spin value other than +-1; the status stays OK. */
+ * bit 2 Sz != 0, bit 4 a spin value other than +-1; the status stays OK.
+ * workspace: dev, at least vqmc_local_energy_workspace bytes (may be NULL
+ * when that is 0). */
 vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                               const int8_t *spins, int32_t B, double *e_loc,
-                              int32_t *chain_flags, hipStream_t stream);
+                              int32_t *chain_flags, void *workspace,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Workspace (device bytes) vqmc_local_energy needs for this model and B
+ * (0 for the dense evaluation). */
+vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes);
 
 /* Workspace (device bytes) needed by vqmc_log_derivs for this model. */
 vqmc_status vqmc_log_derivs_workspace(const vqmc_model *m, int32_t B, size_t *bytes);

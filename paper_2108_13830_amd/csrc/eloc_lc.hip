@@ -1,0 +1,491 @@
+// eloc_lc.hip -- local energy by incremental evaluation inside light cones.
+//
+// For an exchanged configuration s' = s with the pair (i, j) swapped, the
+// input changes on two sites only, so after the l-th 3x3 convolution the
+// activations differ from those of s only within Chebyshev distance l of the
+// pair (its "light cone").  The kernel runs the dense forward pass of s once
+// per sample (FP32), keeps every pre-activation z_l(s) in a per-workgroup
+// scratch slice, and then for each s' propagates only the difference:
+//   dz_l = W_l (*) dh_{l-1}           (matrix cores, rows = cone sites)
+//   dh_l = tanh(z_l + dz_l) - tanh(z_l) = tanh(dz_l) (1 - tanh(z_l) tanh(z_l + dz_l))
+// and log|W(s')| - log|W(s)| = sum over the last cone of dh_{n+1}.  The
+// difference of activations is what enters the convolutions, so rounding it to
+// BF16 (single or split) costs relative precision of the difference, not of
+// the activations.  The local energy is the same sum as in the dense kernel
+// (Eq. Es-Os-G with the bonds of Sec. 3.1).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "eloc_lc.hpp"
+#include "engine.hpp"
+
+namespace vqmc {
+
+namespace {
+
+template <int NW>
+__device__ __forceinline__ double bsum(double v, double *tmp) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += tmp[w];
+  __syncthreads();
+  return t;
+}
+
+template <int NW>
+__device__ __forceinline__ int bisum(int v, int *tmp) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) tmp[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += tmp[w];
+  __syncthreads();
+  return t;
+}
+
+template <int NW>
+__device__ __forceinline__ int bscan(int v, int *tmp, int *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    base += (w < wave) ? tmp[w] : 0;
+    tot += tmp[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + x - v;
+}
+
+// tanh of a small or large argument with relative accuracy: the odd series
+// below 0.1 (truncation < 1e-11 relative), the exponential form above.
+__device__ __forceinline__ float tanh_rel(float b) {
+  const float b2 = b * b;
+  if (fabsf(b) < 0.1f) return b * (1.f - b2 * (1.f / 3.f - b2 * (2.f / 15.f - b2 * (17.f / 315.f))));
+  return tanh_f(b);
+}
+
+// tanh(a + b) - tanh(a) with the relative accuracy of b.
+__device__ __forceinline__ float tanh_diff(float a, float b) {
+  return tanh_rel(b) * (1.f - tanh_f(a) * tanh_f(a + b));
+}
+
+// Unwrapped bounding box of the exchanged pair of bond k: rows y0..y0+ey,
+// columns x0..x0+ex (x0 may be -1 for the lower-left bond).
+__device__ __forceinline__ void pair_box(int k, int L, int N, int &i, int &j, int &kind, int &y0, int &x0,
+                                         int &ey, int &ex) {
+  kind = k / N;
+  const int site = k - kind * N, y = site / L, x = site - y * L;
+  i = site;
+  y0 = y;
+  ey = kind > 0 ? 1 : 0;
+  switch (kind) {
+    case 0: x0 = x; ex = 1; j = y * L + wrapL(x + 1, L); break;
+    case 1: x0 = x; ex = 0; j = wrapL(y + 1, L) * L + x; break;
+    case 2: x0 = x; ex = 1; j = wrapL(y + 1, L) * L + wrapL(x + 1, L); break;
+    default: x0 = x - 1; ex = 1; j = wrapL(y + 1, L) * L + wrapL(x - 1, L); break;
+  }
+}
+
+// The cone box at distance l: start row/col and extent, clipped to the torus.
+struct Box {
+  int ys, xs, H, W;
+  __device__ __forceinline__ void set(int y0, int x0, int ey, int ex, int l, int L) {
+    H = ey + 1 + 2 * l;
+    W = ex + 1 + 2 * l;
+    ys = y0 - l;
+    xs = x0 - l;
+    if (H >= L) {
+      H = L;
+      ys = 0;
+    }
+    if (W >= L) {
+      W = L;
+      xs = 0;
+    }
+  }
+  __device__ __forceinline__ int site(int r, int L) const {
+    const int ry = r / W, rx = r - ry * W;
+    return (((ys + ry) % L + L) % L) * L + (((xs + rx) % L + L) % L);
+  }
+};
+
+template <int C, int PREC, int NW, int TPW>
+struct LC {
+  using E32 = Engine<C, P_F32, NW, TPW>;
+  using EP = Engine<C, PREC, NW, TPW>;
+  static constexpr int NT = E32::NT;
+  static constexpr int ACT = E32::ACT_BYTES > EP::ACT_BYTES ? E32::ACT_BYTES : EP::ACT_BYTES;
+  static constexpr int MR = E32::MAXROWS;
+  static constexpr int FRAG = E32::FRAG_BYTES > EP::FRAG_BYTES ? E32::FRAG_BYTES : EP::FRAG_BYTES;
+};
+
+// Copies one layer's packed fragments (bytes, a multiple of 16) into LDS.
+template <int NTHR>
+__device__ __forceinline__ void stage(char *dst, const char *__restrict__ src, int bytes) {
+  const uint4 *s = reinterpret_cast<const uint4 *>(src);
+  uint4 *d = reinterpret_cast<uint4 *>(dst);
+  for (int i = threadIdx.x; i < bytes / 16; i += NTHR) d[i] = s[i];
+}
+
+template <int C, int PREC, int NW, int TPW>
+__global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restrict__ theta,
+                                                          const char *__restrict__ frag32,
+                                                          const char *__restrict__ fragp,
+                                                          const int8_t *__restrict__ spins, int B, int L,
+                                                          int n_layers, double J1, double J2, int marshall,
+                                                          float *__restrict__ zscratch,
+                                                          double *__restrict__ e_loc,
+                                                          int32_t *__restrict__ flags) {
+  using K = LC<C, PREC, NW, TPW>;
+  using E32 = typename K::E32;
+  using EP = typename K::EP;
+  constexpr int NT = K::NT;
+  constexpr int MR = K::MR;
+  __shared__ __align__(16) char s_act[K::ACT];
+  __shared__ __align__(16) char s_frag[K::FRAG];
+  __shared__ int8_t s_sig[MR];
+  __shared__ int16_t s_bonds[4 * MR];
+  __shared__ double s_red[NW];
+  __shared__ int s_ired[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int N = L * L, NB = 4 * N;
+  const size_t per_frag32 = (size_t)E32::KS * NT * 64 * E32::FRAG;
+  const size_t per_fragp = (size_t)EP::KS * NT * 64 * EP::FRAG;
+  float *zsc = zscratch + (size_t)blockIdx.x * (n_layers + 1) * N * C;
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const int8_t *s = spins + (size_t)b * N;
+    int sz = 0, bad = 0;
+    for (int i = tid; i < N; i += NW * 64) {
+      const int8_t v = s[i];
+      s_sig[i] = v;
+      sz += v;
+      bad += (v != 1 && v != -1);
+    }
+    sz = bisum<NW>(sz, s_ired);
+    bad = bisum<NW>(bad, s_ired);
+    // ---- bond scan (diagonal term, ordered antiparallel list)
+    const int chunk = (NB + NW * 64 - 1) / (NW * 64);
+    const int k0 = tid * chunk, k1 = min(k0 + chunk, NB);
+    double dsum = 0.0;
+    int cnt = 0;
+    for (int k = k0; k < k1; ++k) {
+      int i, j, kind, y0, x0, ey, ex;
+      pair_box(k, L, N, i, j, kind, y0, x0, ey, ex);
+      const int si = s_sig[i], sj = s_sig[j];
+      dsum += 0.25 * (kind < 2 ? J1 : J2) * (double)(si * sj);
+      cnt += (si != sj);
+    }
+    int total;
+    int off = bscan<NW>(cnt, s_ired, &total);
+    for (int k = k0; k < k1; ++k) {
+      int i, j, kind, y0, x0, ey, ex;
+      pair_box(k, L, N, i, j, kind, y0, x0, ey, ex);
+      if (s_sig[i] != s_sig[j]) s_bonds[off++] = (int16_t)k;
+    }
+    const double diag = bsum<NW>(dsum, s_red);
+
+    // ---- dense FP32 forward of s, keeping every pre-activation z_l(s)
+    {
+      const float *W0 = theta, *b0 = theta + 9 * C;
+      for (int idx = tid; idx < N * C; idx += NW * 64) {
+        const int row = idx / C, co = idx - row * C;
+        const int y = row / L, x = row - y * L;
+        float z = b0[co];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+          z += W0[co * 9 + tap] * (float)s_sig[wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L)];
+        zsc[idx] = z;
+        E32::store_act(s_act, row, co, tanh_f(z));
+      }
+      stage<NW * 64>(s_frag, frag32, (int)per_frag32);
+      __syncthreads();
+      for (int l = 1; l <= n_layers; ++l) {
+        f32x4 acc[TPW][NT];
+        E32::template kloop<false, 1>(s_act, s_frag, N, L, N, acc);
+        __syncthreads();
+        if (l < n_layers) stage<NW * 64>(s_frag, frag32 + (size_t)l * per_frag32, (int)per_frag32);
+        const float *bias = theta + layer_offset(C, l) + 9 * C * C;
+        float *zl = zsc + (size_t)l * N * C;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int co = nt * 16 + (lane & 15);
+          const float bv = co < C ? bias[co] : 0.f;
+#pragma unroll
+          for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + jj;
+              if (row < N && co < C) {
+                const float z = acc[i][nt][jj] + bv;
+                zl[row * C + co] = z;
+                if (l < n_layers) E32::store_act(s_act, row, co, tanh_f(z));
+              }
+            }
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---- every exchanged configuration, one at a time
+    double eacc = diag;
+    bool finite = true;
+    for (int q = 0; q < total; ++q) {
+      int bi, bj, kind, y0, x0, ey, ex;
+      pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
+      const float dsi = (float)(s_sig[bj] - s_sig[bi]);  // change of spin at bi (at bj: -dsi)
+      // clear the difference buffer
+      {
+        uint4 *p = reinterpret_cast<uint4 *>(s_act);
+        for (int idx = tid; idx < K::ACT / 16; idx += NW * 64) p[idx] = uint4{0, 0, 0, 0};
+      }
+      stage<NW * 64>(s_frag, fragp, (int)per_fragp);
+      __syncthreads();
+      // lift: dz_1[x][c] = sum_tap W0[c][tap] ds[x + d(tap)] on the distance-1 box
+      {
+        Box bx;
+        bx.set(y0, x0, ey, ex, 1, L);
+        const int R = bx.H * bx.W;
+        for (int idx = tid; idx < R * C; idx += NW * 64) {
+          const int r = idx / C, co = idx - r * C;
+          const int site = bx.site(r, L);
+          const int y = site / L, x = site - y * L;
+          float dz = 0.f;
+#pragma unroll
+          for (int tap = 0; tap < 9; ++tap) {
+            const int nb = wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L);
+            const float w = theta[co * 9 + tap];
+            dz += nb == bi ? w * dsi : (nb == bj ? -w * dsi : 0.f);
+          }
+          EP::store_act(s_act, site, co, tanh_diff(zsc[site * C + co], dz));
+        }
+      }
+      __syncthreads();
+      double part = 0.0;
+      for (int l = 1; l <= n_layers; ++l) {
+        Box bx;
+        bx.set(y0, x0, ey, ex, l + 1, L);
+        const int R = bx.H * bx.W;
+        int pk[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          int r = (wave + i * NW) * 16 + (lane & 15);
+          r = r < R ? r : R - 1;
+          const int site = bx.site(r, L), y = site / L;
+          pk[i] = (y << 5) | (site - y * L);
+        }
+        f32x4 acc[TPW][NT];
+        EP::template kloop_pk<false, 1>(s_act, s_frag, pk, L, acc);
+        __syncthreads();
+        if (l < n_layers) stage<NW * 64>(s_frag, fragp + (size_t)l * per_fragp, (int)per_fragp);
+        const float *zl = zsc + (size_t)l * N * C;
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int T = wave + i * NW;
+          if (T * 16 < R) {
+            // the lane's four output rows r0..r0+3 walk the box row-major
+            const int r0 = T * 16 + (lane >> 4) * 4;
+            int ry = r0 / bx.W, rx = r0 - ry * bx.W;
+            int y = bx.ys + ry, x = bx.xs + rx;
+            y = y < 0 ? y + L : (y >= L ? y - L : y);
+            x = x < 0 ? x + L : (x >= L ? x - L : x);
+            int site[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              site[jj] = y * L + x;
+              ++rx;
+              x = x + 1 == L ? 0 : x + 1;
+              if (rx == bx.W) {
+                rx = 0;
+                x = bx.xs < 0 ? bx.xs + L : bx.xs;
+                y = y + 1 == L ? 0 : y + 1;
+              }
+            }
+            // all pre-activations of the tile first (in-bounds for every
+            // lane: rows past the box reuse a valid site), then the updates
+            float za[4][NT];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+              for (int nt = 0; nt < NT; ++nt) {
+                const int co = nt * 16 + (lane & 15);
+                za[jj][nt] = zl[site[jj] * C + (co < C ? co : 0)];
+              }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              if (r0 + jj < R) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                  const int co = nt * 16 + (lane & 15);
+                  if (co < C) {
+                    const float dh = tanh_diff(za[jj][nt], acc[i][nt][jj]);
+                    if (l < n_layers) EP::store_act(s_act, site[jj], co, dh);
+                    else part += (double)dh;
+                  }
+                }
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      const double dlog = bsum<NW>(part, s_red);
+      const double J = kind < 2 ? J1 : J2;
+      const double mu = (marshall && kind < 2) ? -1.0 : 1.0;
+      const double term = 0.5 * J * mu * exp(dlog);
+      finite = finite && isfinite(dlog);
+      eacc += term;
+    }
+    if (tid == 0) {
+      e_loc[b] = eacc;
+      if (flags) flags[b] = ((!isfinite(eacc) || !finite) ? 1 : 0) | (sz != 0 ? 2 : 0) | (bad ? 4 : 0);
+    }
+    __syncthreads();
+  }
+}
+
+// Packs the C -> C layers' weights in the engine's per-lane fragment order
+// for precision PREC: [layer][KS][NT][64] fragments.
+template <int C, int PREC>
+__global__ void pack_lc_kernel(const float *__restrict__ theta, int n_layers, char *__restrict__ out) {
+  using E = Engine<C, PREC, 1, 1>;
+  constexpr int PER = E::KS * E::NT * 64;
+  const int total = n_layers * PER;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int l = t / PER + 1, idx = t - (l - 1) * PER;
+    const int s = idx / (E::NT * 64), r2 = idx - s * (E::NT * 64);
+    const int nt = r2 >> 6, ln = r2 & 63;
+    const int n = nt * 16 + (ln & 15);
+    const float *W = theta + layer_offset(C, l);
+    char *dst = out + (size_t)t * E::FRAG;
+    if constexpr (PREC == P_F32) {
+      *reinterpret_cast<float *>(dst) = E::wsel(W, 4 * s + (ln >> 4), n);
+    } else {
+      const int k0 = 32 * s + 8 * (ln >> 4);
+      u16x8 hi, lo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float w = E::wsel(W, k0 + j, n);
+        hi[j] = bf16_rne(w);
+        lo[j] = bf16_rne(w - bf16_f32(hi[j]));
+      }
+      reinterpret_cast<u16x8 *>(dst)[0] = hi;
+      if constexpr (PREC == P_X3) reinterpret_cast<u16x8 *>(dst)[1] = lo;
+    }
+  }
+}
+
+template <int C, int PREC>
+constexpr size_t frag_bytes_per_layer() {
+  using E = Engine<C, PREC, 1, 1>;
+  return (size_t)E::KS * E::NT * 64 * E::FRAG;
+}
+
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+int lc_tpw(int N) { return N <= 64 ? 1 : N <= 128 ? 2 : N <= 256 ? 4 : 9; }
+
+template <int C, int PREC, int TPW>
+int lc_grid(int B) {
+  const int lds = LC<C, PREC, 4, TPW>::ACT + LC<C, PREC, 4, TPW>::FRAG + 5 * LC<C, PREC, 4, TPW>::MR + 256;
+  int per_cu = 160 * 1024 / lds;
+  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+  const int g = 256 * per_cu;
+  return B < g ? B : g;
+}
+
+template <int C, int PREC>
+int lc_grid_c(int N, int B) {
+  switch (lc_tpw(N)) {
+    case 1: return lc_grid<C, PREC, 1>(B);
+    case 2: return lc_grid<C, PREC, 2>(B);
+    case 4: return lc_grid<C, PREC, 4>(B);
+    default: return lc_grid<C, PREC, 9>(B);
+  }
+}
+
+template <int C, int PREC>
+size_t lc_ws(const vqmc_model *m, int B) {
+  const int N = m->L * m->L, n = m->n_layers;
+  const int grid = B > 0 ? lc_grid_c<C, PREC>(N, B) : 0;
+  return al256(n * frag_bytes_per_layer<C, P_F32>()) + al256(n * frag_bytes_per_layer<C, PREC>()) +
+         (size_t)grid * (n + 1) * N * C * 4;
+}
+
+template <int C, int PREC, int TPW>
+vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
+                      int32_t *flags, char *ws, hipStream_t st) {
+  const int n = m->n_layers;
+  char *f32 = ws;
+  char *fp = ws + al256(n * frag_bytes_per_layer<C, P_F32>());
+  float *z = reinterpret_cast<float *>(fp + al256(n * frag_bytes_per_layer<C, PREC>()));
+  const int t32 = n * Engine<C, P_F32, 1, 1>::KS * Engine<C, P_F32, 1, 1>::NT * 64;
+  const int tp = n * Engine<C, PREC, 1, 1>::KS * Engine<C, PREC, 1, 1>::NT * 64;
+  pack_lc_kernel<C, P_F32><<<(t32 + 255) / 256, 256, 0, st>>>(theta, n, f32);
+  if (PREC != P_F32) pack_lc_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
+  else fp = f32;
+  eloc_lc_kernel<C, PREC, 4, TPW><<<lc_grid<C, PREC, TPW>(B), 256, 0, st>>>(
+      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags);
+  if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
+  return VQMC_OK;
+}
+
+template <int C, int PREC>
+vqmc_status lc_launch_c(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
+                        int32_t *flags, char *ws, hipStream_t st) {
+  switch (lc_tpw(m->L * m->L)) {
+    case 1: return lc_launch<C, PREC, 1>(m, theta, spins, B, e_loc, flags, ws, st);
+    case 2: return lc_launch<C, PREC, 2>(m, theta, spins, B, e_loc, flags, ws, st);
+    case 4: return lc_launch<C, PREC, 4>(m, theta, spins, B, e_loc, flags, ws, st);
+    default: return lc_launch<C, PREC, 9>(m, theta, spins, B, e_loc, flags, ws, st);
+  }
+}
+
+}  // namespace
+
+size_t eloc_lc_workspace(const vqmc_model *m, int B) {
+  switch (m->channels) {
+    case 16:
+      return m->conv_prec == P_F32 ? lc_ws<16, P_F32>(m, B)
+                                   : m->conv_prec == P_BF16 ? lc_ws<16, P_BF16>(m, B) : lc_ws<16, P_X3>(m, B);
+    case 32:
+      return m->conv_prec == P_F32 ? lc_ws<32, P_F32>(m, B)
+                                   : m->conv_prec == P_BF16 ? lc_ws<32, P_BF16>(m, B) : lc_ws<32, P_X3>(m, B);
+    default: return 0;
+  }
+}
+
+bool eloc_lc_supported(const vqmc_model *m) { return m->channels == 16 || m->channels == 32; }
+
+vqmc_status eloc_lc(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
+                    int32_t *flags, void *ws, hipStream_t st) {
+  char *w = reinterpret_cast<char *>(ws);
+  switch (m->channels) {
+    case 16:
+      return m->conv_prec == P_F32 ? lc_launch_c<16, P_F32>(m, theta, spins, B, e_loc, flags, w, st)
+             : m->conv_prec == P_BF16 ? lc_launch_c<16, P_BF16>(m, theta, spins, B, e_loc, flags, w, st)
+                                      : lc_launch_c<16, P_X3>(m, theta, spins, B, e_loc, flags, w, st);
+    case 32:
+      return m->conv_prec == P_F32 ? lc_launch_c<32, P_F32>(m, theta, spins, B, e_loc, flags, w, st)
+             : m->conv_prec == P_BF16 ? lc_launch_c<32, P_BF16>(m, theta, spins, B, e_loc, flags, w, st)
+                                      : lc_launch_c<32, P_X3>(m, theta, spins, B, e_loc, flags, w, st);
+    default: return VQMC_ERR_ARG;
+  }
+}
+
+}  // namespace vqmc

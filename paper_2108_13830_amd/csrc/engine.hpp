@@ -174,9 +174,20 @@ struct Engine {
       r = r < R ? r : R - 1;
       const int g = r / N, site = r - g * N, y = site / L;
       pk[i] = ((g * N) << 10) | (y << 5) | (site - y * L);
+    }
+    kloop_pk<FRAG_GLOBAL, SIGN>(act, frag, pk, L, acc);
+  }
+
+  // The same K loop for rows given directly as packed (row base, y, x):
+  // tile i of this wave reads the lane's row pk[i].
+  template <bool FRAG_GLOBAL, int SIGN>
+  __device__ static __forceinline__ void kloop_pk(const char *act, const char *frag, const int (&pk)[TPW],
+                                                  int L, f32x4 (&acc)[TPW][NT]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
     if constexpr (F32) {
       const float *actf = reinterpret_cast<const float *>(act);
       const float *fragf = reinterpret_cast<const float *>(frag);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "common.hpp"
+#include "eloc_lc.hpp"
 #include "engine.hpp"
 
 namespace vqmc {
@@ -434,12 +435,33 @@ extern "C" vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta, con
   return dispatch(K_LOGPSI, m->channels, m->conv_prec, a);
 }
 
+// Light cones pay off once they stay well inside the lattice for most layers.
+static bool use_lightcone(const vqmc_model *m) {
+  if (m->eloc_mode == VQMC_ELOC_DENSE) return false;
+  if (!eloc_lc_supported(m)) return false;
+  return m->eloc_mode == VQMC_ELOC_LIGHTCONE || m->L >= 14;
+}
+
+extern "C" vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes) {
+  if (!model_valid(m) || !bytes) return VQMC_ERR_ARG;
+  if (B < 0) return VQMC_ERR_SHAPE;
+  if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
+  *bytes = use_lightcone(m) ? eloc_lc_workspace(m, B) : 0;
+  return VQMC_OK;
+}
+
 extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                                          const int8_t *spins, int32_t B, double *e_loc,
-                                         int32_t *chain_flags, hipStream_t stream) {
+                                         int32_t *chain_flags, void *workspace, size_t ws_bytes,
+                                         hipStream_t stream) {
   if (!model_valid(m)) return VQMC_ERR_ARG;
   if (B < 0) return VQMC_ERR_SHAPE;
+  if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
   if (B > 0 && (!theta || !spins || !e_loc)) return VQMC_ERR_ARG;
+  if (B > 0 && use_lightcone(m)) {
+    if (!workspace || ws_bytes < eloc_lc_workspace(m, B)) return VQMC_ERR_WORKSPACE;
+    return eloc_lc(m, theta, spins, B, e_loc, chain_flags, workspace, stream);
+  }
   FwdArgs a{};
   a.theta = theta;
   a.spins_in = spins;

@@ -1,0 +1,77 @@
+// tile128.hpp -- 128 x 128 output tile of C += A B^T on the matrix cores,
+// with A and B staged in LDS as [128][KC] panels (rows of A and rows of B,
+// K contiguous).  256 threads = 4 waves in 2 x 2, each wave a 64 x 64
+// sub-tile of 4 x 4 instruction tiles (16 x 16).  Used by the explicit S
+// (FP64 or FP32), the sample-space Gram matrix and the Cholesky trailing
+// update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "engine.hpp"
+
+namespace vqmc {
+
+template <typename T>
+struct Tile128 {
+  static constexpr bool F64 = sizeof(T) == 8;
+  using acc_t = typename std::conditional<F64, f64x4, f32x4>::type;
+
+  __device__ static __forceinline__ acc_t mma(T a, T b, acc_t c) {
+    if constexpr (F64) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+
+  __device__ static __forceinline__ void zero(acc_t (&acc)[4][4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  }
+
+  // acc += sA[wm*64 .. +63][0..KC) * sB[wn*64 .. +63][0..KC)^T
+  template <int KC, int LD>
+  __device__ static __forceinline__ void step(const T (*sA)[LD], const T (*sB)[LD], acc_t (&acc)[4][4]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll 2
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      T a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = sA[wm * 64 + t * 16 + (lane & 15)][k];
+        b[t] = sB[wn * 64 + t * 16 + (lane & 15)][k];
+      }
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = mma(a[tm], b[tn], acc[tm][tn]);
+    }
+  }
+
+  // Row and column (within the 128 x 128 tile) held by register r of
+  // instruction tile (tm, tn) in this lane.  FP64 16x16x4: row l/16 + 4r;
+  // FP32 16x16x4: row 4(l/16) + r; column l%16 for both.
+  __device__ static __forceinline__ int row_of(int tm, int r) {
+    const int lane = threadIdx.x & 63, wm = (threadIdx.x >> 6) >> 1;
+    return wm * 64 + tm * 16 + (F64 ? ((lane >> 4) + 4 * r) : (4 * (lane >> 4) + r));
+  }
+  __device__ static __forceinline__ int col_of(int tn) {
+    const int lane = threadIdx.x & 63, wn = (threadIdx.x >> 6) & 1;
+    return wn * 64 + tn * 16 + (lane & 15);
+  }
+};
+
+// Index (bi >= bj) of the t-th block of a lower block triangle.
+__device__ __forceinline__ void lower_block(int t, int &bi, int &bj) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  bi = i;
+  bj = t - i * (i + 1) / 2;
+}
+
+}  // namespace vqmc

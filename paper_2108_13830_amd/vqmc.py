@@ -21,6 +21,7 @@ PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2
 PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16x3": PREC_BF16X3}
 
 SR_AUTO, SR_CHOLESKY, SR_CG, SR_DUAL = 0, 1, 2, 3
+ELOC_AUTO, ELOC_DENSE, ELOC_LIGHTCONE = 0, 1, 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported size", 3: "device error",
           4: "workspace too small", 5: "matrix not positive definite",
@@ -37,7 +38,7 @@ class VqmcError(RuntimeError):
 class _Model(ct.Structure):
     _fields_ = [("L", ct.c_int32), ("channels", ct.c_int32), ("n_layers", ct.c_int32),
                 ("activation", ct.c_int32), ("J1", ct.c_double), ("J2", ct.c_double),
-                ("marshall", ct.c_int32), ("conv_prec", ct.c_int32)]
+                ("marshall", ct.c_int32), ("conv_prec", ct.c_int32), ("eloc_mode", ct.c_int32)]
 
 
 class _SrOpts(ct.Structure):
@@ -61,13 +62,17 @@ class Model:
     J2: float = 0.5
     marshall: int = 1
     prec: int = PREC_FP32
+    eloc: int = ELOC_AUTO
 
     def c(self) -> _Model:
-        return _Model(self.L, self.C, self.n, 0, self.J1, self.J2, self.marshall, self.prec)
+        return _Model(self.L, self.C, self.n, 0, self.J1, self.J2, self.marshall, self.prec, self.eloc)
 
     def with_prec(self, prec) -> "Model":
         p = PREC_NAMES[prec] if isinstance(prec, str) else prec
-        return Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, p)
+        return Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, p, self.eloc)
+
+    def with_eloc(self, eloc) -> "Model":
+        return Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, self.prec, eloc)
 
     @property
     def N(self) -> int:
@@ -96,7 +101,10 @@ SIGNATURES = [
     ("vqmc_sample", ct.c_int, [ct.POINTER(_Model), _VP, _VP, _VP, ct.c_int32, ct.c_int32,
                                ct.c_uint64, ct.c_uint64, ct.c_int32, _VP, _VP]),
     ("vqmc_log_psi", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP]),
-    ("vqmc_local_energy", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP]),
+    ("vqmc_local_energy", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP,
+                                     ct.c_size_t, _VP]),
+    ("vqmc_local_energy_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32,
+                                               ct.POINTER(ct.c_size_t)]),
     ("vqmc_log_derivs_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32,
                                              ct.POINTER(ct.c_size_t)]),
     ("vqmc_log_derivs", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, ct.c_int64,
@@ -178,7 +186,15 @@ def vqmc_log_psi(m: Model, theta, spins, out=None, sign=None):
     return out
 
 
-def vqmc_local_energy(m: Model, theta, spins, out=None, flags=None):
+def local_energy_workspace(m: Model, B: int) -> int:
+    mc = m.c()
+    n = ct.c_size_t(0)
+    _check("vqmc_local_energy_workspace", lib().vqmc_local_energy_workspace(ct.byref(mc), B,
+                                                                            ct.byref(n)))
+    return n.value
+
+
+def vqmc_local_energy(m: Model, theta, spins, out=None, flags=None, workspace=None):
     B = spins.shape[0]
     _dev(theta, torch.float32, "theta", (num_params(m),))
     _dev(spins, torch.int8, "spins", (B, m.N))
@@ -186,9 +202,13 @@ def vqmc_local_energy(m: Model, theta, spins, out=None, flags=None):
         out = torch.empty(B, dtype=torch.float64, device=spins.device)
     _dev(out, torch.float64, "out", (B,))
     _dev(flags, torch.int32, "flags", (B,))
+    ws = local_energy_workspace(m, B)
+    if workspace is None and ws > 0:
+        workspace = torch.empty(ws, dtype=torch.uint8, device=spins.device)
     mc = m.c()
-    _check("vqmc_local_energy", lib().vqmc_local_energy(ct.byref(mc), _ptr(theta), _ptr(spins), B,
-                                                        _ptr(out), _ptr(flags), _stream()))
+    _check("vqmc_local_energy", lib().vqmc_local_energy(
+        ct.byref(mc), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(flags), _ptr(workspace),
+        0 if workspace is None else workspace.numel(), _stream()))
     return out
 
 

@@ -23,7 +23,7 @@ def declared():
 
 def test_every_declared_symbol_is_exported():
     names = declared()
-    assert len(names) == 9
+    assert len(names) == 10
     lib = ct.CDLL(V.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -36,6 +36,7 @@ def test_num_params_and_model_validation():
     assert V.num_params(V.Model(10, 16, 6)) == 14080
     assert V.num_params(V.Model(24, 32, 8)) == 74304
     for bad in (V.Model(5, 4, 2), V.Model(26, 4, 2), V.Model(4, 12, 2), V.Model(4, 4, 0),
+                V.Model(4, 4, 2, eloc=3),
                 V.Model(4, 4, 2, prec=V.PREC_BF16), V.Model(4, 8, 2, prec=7), V.Model(4, 8, 2, marshall=2)):
         assert V.num_params(bad) == -1
 
@@ -53,12 +54,22 @@ def test_argument_errors_need_no_gpu():
     good = V.Model(4, 4, 2).c()
     nul = ct.c_void_p(0)
     assert lib.vqmc_log_psi(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
-    assert lib.vqmc_local_energy(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
+    assert lib.vqmc_local_energy(ct.byref(bad), nul, nul, 1, nul, nul, nul, 0, nul) == 1
     assert lib.vqmc_log_psi(ct.byref(good), nul, nul, -1, nul, nul, nul) == 2
     assert lib.vqmc_log_psi(ct.byref(good), nul, nul, 3, nul, nul, nul) == 1
     # B = 0 is a valid empty call: nothing is launched
     assert lib.vqmc_log_psi(ct.byref(good), nul, nul, 0, nul, nul, nul) == 0
-    assert lib.vqmc_local_energy(ct.byref(good), nul, nul, 0, nul, nul, nul) == 0
+    assert lib.vqmc_local_energy(ct.byref(good), nul, nul, 0, nul, nul, nul, 0, nul) == 0
+    # the light-cone evaluation needs 16 or 32 channels and a workspace
+    lc = V.Model(16, 32, 8, eloc=V.ELOC_LIGHTCONE).c()
+    n = ct.c_size_t(0)
+    assert lib.vqmc_local_energy_workspace(ct.byref(lc), 64, ct.byref(n)) == 0 and n.value > 0
+    assert lib.vqmc_local_energy(ct.byref(lc), ct.c_void_p(8), ct.c_void_p(8), 64, ct.c_void_p(8), nul,
+                                 nul, 0, nul) == 4
+    lc4 = V.Model(16, 4, 2, eloc=V.ELOC_LIGHTCONE).c()
+    assert lib.vqmc_local_energy_workspace(ct.byref(lc4), 64, ct.byref(n)) == 1
+    dense = V.Model(16, 32, 8, eloc=V.ELOC_DENSE).c()
+    assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 0
     assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 2, 1, 0, 0, 5, nul, nul) == 1
     assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 0, 1, 0, 0, 0, nul, nul) == 0
     n = ct.c_size_t(0)
