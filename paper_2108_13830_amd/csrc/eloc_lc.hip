@@ -135,6 +135,20 @@ struct LC {
   static constexpr int FRAG = E32::FRAG_BYTES > EP::FRAG_BYTES ? E32::FRAG_BYTES : EP::FRAG_BYTES;
 };
 
+// The engine's K loop over the first n tile slots only (n wave-uniform,
+// 0 <= n <= TPW), dispatched to a compile-time trip count.
+template <class EP, int TPW, int K = 1>
+__device__ __forceinline__ void kloop_n(int n, const char *act, const char *frag, const int (&pk)[TPW], int L,
+                                        f32x4 (&acc)[TPW][EP::NT]) {
+  if constexpr (K <= TPW) {
+    if (n <= K) {
+      EP::template kloop_pk<false, 1, K>(act, frag, pk, L, acc);
+      return;
+    }
+    kloop_n<EP, TPW, K + 1>(n, act, frag, pk, L, acc);
+  }
+}
+
 // Copies one layer's packed fragments (bytes, a multiple of 16) into LDS.
 template <int NTHR>
 __device__ __forceinline__ void stage(char *dst, const char *__restrict__ src, int bytes) {
@@ -290,7 +304,10 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
           pk[i] = (y << 5) | (site - y * L);
         }
         f32x4 acc[TPW][NT];
-        EP::template kloop_pk<false, 1>(s_act, s_frag, pk, L, acc);
+        // tiles of this wave in the current box (wave-uniform)
+        const int Ttot = (R + 15) / 16;
+        const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
+        kloop_n<EP, TPW>(nti, s_act, s_frag, pk, L, acc);
         __syncthreads();
         if (l < n_layers) stage<NW * 64>(s_frag, fragp + (size_t)l * per_fragp, (int)per_fragp);
         const float *zl = zsc + (size_t)l * N * C;

@@ -50,11 +50,12 @@ __device__ __forceinline__ f32x4 mma_bf16(u16x8 a, u16x8 b, f32x4 c) {
                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// tanh(x) = 1 - 2 / (exp(2x) + 1): one exponential and one reciprocal;
-// absolute error ~1e-7 over the whole real line (saturates to +-1).
+// tanh(x) = 1 - 2 / (exp(2x) + 1): one exponential and one hardware
+// reciprocal (1 ulp); absolute error ~2e-7 over the whole real line
+// (saturates to +-1).
 __device__ __forceinline__ float tanh_f(float x) {
   const float e = __expf(2.f * x);
-  return 1.f - __fdividef(2.f, e + 1.f);
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -79,11 +80,12 @@ struct Engine {
   static constexpr int FRAG = F32 ? 4 : (X3 ? 32 : 16);
   static constexpr int NTHR = NW * 64;
   static constexpr int MAXROWS = NW * TPW * 16;
-  static constexpr int ACT_BYTES =
-      F32 ? MAXROWS * LDA * 4 : MAXROWS * C * 2 * (X3 ? 2 : 1);
+  // FP32: padded rows; BF16 forms: hi (and lo) planes.  At least
+  // MAXROWS * C floats, which the head reuses for the last layer's outputs.
+  static constexpr int ACT_BYTES = F32 ? MAXROWS * LDA * 4 : MAXROWS * C * 4;
   static constexpr int FRAG_BYTES = KS * NT * 64 * FRAG;
   static_assert(F32 ? (C % 4 == 0) : (C % 8 == 0), "channel count not supported");
-  static_assert(8 * MAXROWS <= ACT_BYTES, "row sums must fit the activation buffer");
+  static_assert(MAXROWS * C * 4 <= ACT_BYTES, "the head reuses the activation buffer");
 
   // BF16 activation planes: 8-element groups XOR-swizzled by the row so that
   // the 16 rows of a tile spread over the LDS banks.
@@ -179,8 +181,9 @@ struct Engine {
   }
 
   // The same K loop for rows given directly as packed (row base, y, x):
-  // tile i of this wave reads the lane's row pk[i].
-  template <bool FRAG_GLOBAL, int SIGN>
+  // tile i of this wave reads the lane's row pk[i].  Only the first NTILE
+  // tile slots are computed (NTILE <= TPW, compile time).
+  template <bool FRAG_GLOBAL, int SIGN, int NTILE = TPW>
   __device__ static __forceinline__ void kloop_pk(const char *act, const char *frag, const int (&pk)[TPW],
                                                   int L, f32x4 (&acc)[TPW][NT]) {
     const int lane = threadIdx.x & 63;
@@ -188,32 +191,43 @@ struct Engine {
     for (int i = 0; i < TPW; ++i)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Software-pipelined: the A operands of K-step s+1 are requested from
+    // LDS before the matrix instructions of step s are issued.  Every tile
+    // slot runs (rows past R are clamped copies whose results are never
+    // stored), so no branch separates the loads from the matrix
+    // instructions.
     if constexpr (F32) {
       const float *actf = reinterpret_cast<const float *>(act);
       const float *fragf = reinterpret_cast<const float *>(frag);
-      for (int tap = 0; tap < 9; ++tap) {
-        const int dy = SIGN * (tap / 3 - 1), dx = SIGN * (tap % 3 - 1);
-        int nbo[TPW];
+      constexpr int SPT = C / 4;  // K-steps per tap
+      int nbo[NTILE];
+      float a_cur[NTILE], a_nxt[NTILE];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i)
-          nbo[i] = nbrow(pk[i], dy, dx, L) * LDA + (lane >> 4);
+      for (int i = 0; i < NTILE; ++i) {
+        nbo[i] = nbrow(pk[i], -SIGN, -SIGN, L) * LDA + (lane >> 4);
+        a_cur[i] = actf[nbo[i]];
+      }
 #pragma unroll 2
-        for (int c4 = 0; c4 < C / 4; ++c4) {
-          const int s = tap * (C / 4) + c4;
-          float b[NT];
+      for (int s = 0; s < KS; ++s) {
+        float b[NT];
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64 + lane];
-          // every tile slot runs (rows past R are clamped copies whose
-          // results are never stored): no branch between the loads and the
-          // matrix instructions
-          float a[TPW];
+        for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64 + lane];
+        if (s + 1 < KS) {
+          const int s1 = s + 1, tap1 = s1 / SPT, c41 = s1 - tap1 * SPT;
+          if (c41 == 0) {
+            const int dy = SIGN * (tap1 / 3 - 1), dx = SIGN * (tap1 % 3 - 1);
 #pragma unroll
-          for (int i = 0; i < TPW; ++i) a[i] = actf[nbo[i] + c4 * 4];
+            for (int i = 0; i < NTILE; ++i) nbo[i] = nbrow(pk[i], dy, dx, L) * LDA + (lane >> 4);
+          }
 #pragma unroll
-          for (int i = 0; i < TPW; ++i)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a[i], b[nt], acc[i][nt]);
+          for (int i = 0; i < NTILE; ++i) a_nxt[i] = actf[nbo[i] + c41 * 4];
         }
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a_cur[i], b[nt], acc[i][nt]);
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i) a_cur[i] = a_nxt[i];
       }
     } else {
       const uint16_t *hi = reinterpret_cast<const uint16_t *>(act);
@@ -230,21 +244,23 @@ struct Engine {
         const int tap = kv ? k0 / C : 0, ci0 = kv ? k0 - tap * C : 0;
         const int dy = SIGN * (tap / 3 - 1), dx = SIGN * (tap % 3 - 1);
         // lanes whose K slice lies past 9C read row 0 and multiply zero weights
+        u16x8 ah[NTILE], al[NTILE];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
+        for (int i = 0; i < NTILE; ++i) {
           const int nb = kv ? nbrow(pk[i], dy, dx, L) : 0;
-          const u16x8 ah = *reinterpret_cast<const u16x8 *>(hi + phys(nb, ci0));
-          u16x8 al;
-          if constexpr (X3) al = *reinterpret_cast<const u16x8 *>(hi + MAXROWS * C + phys(nb, ci0));
+          ah[i] = *reinterpret_cast<const u16x8 *>(hi + phys(nb, ci0));
+          if constexpr (X3) al[i] = *reinterpret_cast<const u16x8 *>(hi + MAXROWS * C + phys(nb, ci0));
+        }
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
-            acc[i][nt] = mma_bf16(ah, bh[nt], acc[i][nt]);
+            acc[i][nt] = mma_bf16(ah[i], bh[nt], acc[i][nt]);
             if constexpr (X3) {
-              acc[i][nt] = mma_bf16(ah, bl[nt], acc[i][nt]);
-              acc[i][nt] = mma_bf16(al, bh[nt], acc[i][nt]);
+              acc[i][nt] = mma_bf16(ah[i], bl[nt], acc[i][nt]);
+              acc[i][nt] = mma_bf16(al[i], bh[nt], acc[i][nt]);
             }
           }
-        }
       }
     }
   }
@@ -274,33 +290,22 @@ struct Engine {
     }
   }
 
-  // Row sums of tanh(acc + bias) over channels, in FP64, into rowsum[row].
-  __device__ static __forceinline__ void head_rows(const f32x4 (&acc)[TPW][NT], const float *bias,
-                                                   int R, double *rowsum) {
+  // The last layer's outputs tanh(acc + bias) as floats hv[row][C] (the
+  // activation buffer, free once every wave has finished the layer's K loop).
+  __device__ static __forceinline__ void head_vals(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
+                                                   float *hv) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float bv[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int co = nt * 16 + (lane & 15);
-      bv[nt] = co < C ? bias[co] : 0.f;
-    }
+      const float bv = co < C ? bias[co] : 0.f;
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-      const int T = wave + i * NW;
-      if (T * 16 < R) {
+      for (int i = 0; i < TPW; ++i) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double v = 0.0;
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-          if (nt * 16 + (lane & 15) < C) v += (double)tanh_f(acc[i][nt][j] + bv[nt]);
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        const int row = T * 16 + (lane >> 4) * 4 + j;
-        if ((lane & 15) == 0 && row < R) rowsum[row] = v;
-      }
+        for (int j = 0; j < 4; ++j) {
+          const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + j;
+          if (row < R && co < C) hv[row * C + co] = tanh_f(acc[i][nt][j] + bv);
+        }
       }
     }
   }
@@ -323,15 +328,17 @@ struct Engine {
         write_tiles(acc, bias, R, smem_act, nullptr);
         stage_weights(theta + layer_offset(C, l + 1), smem_frag);
       } else {
-        head_rows(acc, bias, R, reinterpret_cast<double *>(smem_act));
+        head_vals(acc, bias, R, reinterpret_cast<float *>(smem_act));
       }
       __syncthreads();
     }
-    const double *rowsum = reinterpret_cast<const double *>(smem_act);
+    // log|W_CNN| of each configuration: its N*C outputs summed in FP64 in a
+    // fixed order (lane-strided partial sums, then the wave's xor tree)
+    const float *hv = reinterpret_cast<const float *>(smem_act);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int g = wave; g < G; g += NW) {
       double p = 0.0;
-      for (int r = lane; r < N; r += 64) p += rowsum[g * N + r];
+      for (int idx = lane; idx < N * C; idx += 64) p += (double)hv[g * N * C + idx];
       p = wave_sum(p);
       if (lane == 0) lp[g] = p;
     }

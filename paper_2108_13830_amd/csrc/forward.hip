@@ -94,7 +94,7 @@ __device__ __forceinline__ void philox(uint32_t &c0, uint32_t &c1, uint32_t &c2,
 // ------------------------------------------------------------- log |psi|
 
 template <int C, int PREC, int NW, int TPW>
-__global__ __launch_bounds__(NW * 64) void logpsi_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void logpsi_kernel(const float *__restrict__ theta,
                                                          const int8_t *__restrict__ spins, int B,
                                                          int L, int n_layers, int marshall, int G,
                                                          double *__restrict__ out,
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(NW * 64) void logpsi_kernel(const float *__restrict
 // engine in batches of G, and the off-diagonal terms J/2 mu exp(dlog) are
 // accumulated in FP64 in bond order.
 template <int C, int PREC, int NW, int TPW>
-__global__ __launch_bounds__(NW * 64) void eloc_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void eloc_kernel(const float *__restrict__ theta,
                                                        const int8_t *__restrict__ spins, int B, int L,
                                                        int n_layers, double J1, double J2,
                                                        int marshall, int G,
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
 template <int C>
 struct Inst {
   static constexpr int NW = 4;
-  static constexpr int TPW = (C == 32) ? 9 : 16;  // rows per block: 576 / 1024
+  static constexpr int TPW = (C == 32) ? 9 : 8;  // rows per block: 576 / 512
   static constexpr int SNW = 1;                   // sampler, small lattices
   static constexpr int STPW = 9;                  // 144 rows
 };
