@@ -170,41 +170,111 @@ __global__ void col_sum_kernel(const double *__restrict__ part, int nch, int64_t
 
 // ------------------------------------------------ explicit S (primal SYRK)
 
-// S[i][j] = (1/B) sum_b (O[b][i] - <O_i>)(O[b][j] - <O_j>) + eps [i == j],
-// lower 128 x 128 blocks.  T = double: FP64 operands and accumulation;
-// T = float: the centred values are rounded to FP32 and accumulated by the
-// FP32 matrix cores.
-template <typename T>
-__global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
-                                                   const double *__restrict__ obar, double eps,
-                                                   double *__restrict__ S) {
-  constexpr int KC = 32;
-  __shared__ T sA[128][KC + 1];
-  __shared__ T sB[128][KC + 1];
-  using TT = Tile128<T>;
-  int bi, bj;
-  lower_block(blockIdx.x, bi, bj);
-  const int64_t i0 = (int64_t)bi * 128, j0 = (int64_t)bj * 128;
-  const int tid = threadIdx.x;
-  const int lc = tid & 127, lr = tid >> 7;  // column within the tile, 2 rows per pass
-  const double obi = (i0 + lc < P) ? obar[i0 + lc] : 0.0;
-  const double obj = (j0 + lc < P) ? obar[j0 + lc] : 0.0;
-  typename TT::acc_t acc[4][4];
-  TT::zero(acc);
-  for (int kb = 0; kb < B; kb += KC) {
-#pragma unroll 4
-    for (int q = 0; q < KC / 2; ++q) {
-      const int r = lr + 2 * q, b = kb + r;
-      const bool rv = b < B;
-      const double vi = (rv && i0 + lc < P) ? (double)O[(int64_t)b * ldO + i0 + lc] - obi : 0.0;
-      const double vj = (rv && j0 + lc < P) ? (double)O[(int64_t)b * ldO + j0 + lc] - obj : 0.0;
-      sA[lc][r] = (T)vi;
-      sB[lc][r] = (T)vj;
+// Loader of the primal S tiles: panel rows are columns ia0.. (A side) or
+// ib0.. (B side) of O, k runs over samples.  Each thread holds four adjacent
+// columns (fixed for the whole K loop) of KC/8 samples per chunk; samples past
+// B are zeroed at the LDS store, columns past P are clamped (they only feed
+// outputs that are not stored).  Centring happens in FP64 before the
+// rounding to T.
+template <typename T, int KC, bool VEC>
+struct SyrkLoader {
+  static constexpr int NQ = KC / 8;
+  const float *O;
+  int64_t ldO;
+  int B;
+  int64_t P, ia0, ib0;
+  double oba[4], obb[4];
+  struct Regs {
+    float v[NQ][4];
+    int c;
+  };
+  __device__ SyrkLoader(const float *O_, int64_t ldO_, int B_, int64_t P_, int64_t ia, int64_t ib,
+                        const double *__restrict__ obar)
+      : O(O_), ldO(ldO_), B(B_), P(P_), ia0(ia), ib0(ib) {
+    const int m4 = threadIdx.x & 31;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t ca = ia0 + 4 * m4 + t, cb = ib0 + 4 * m4 + t;
+      oba[t] = ca < P ? obar[ca] : 0.0;
+      obb[t] = cb < P ? obar[cb] : 0.0;
     }
+  }
+  __device__ __forceinline__ void load(Regs &r, int c, bool bside) const {
+    const int m4 = threadIdx.x & 31;
+    const int64_t col = (bside ? ib0 : ia0) + 4 * m4;
+    r.c = c;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = (threadIdx.x >> 5) + 8 * q;
+      const int b = c * KC + k;
+      const float *row = O + (int64_t)(b < B ? b : B - 1) * ldO;
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4 *>(row + (col <= P - 4 ? col : P - 4));
+        r.v[q][0] = x.x; r.v[q][1] = x.y; r.v[q][2] = x.z; r.v[q][3] = x.w;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r.v[q][t] = row[col + t < P ? col + t : P - 1];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const Regs &r, Panel<T, KC, true> &Pn, bool bside) const {
+    const int m4 = threadIdx.x & 31;
+    const double *ob = bside ? obb : oba;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = (threadIdx.x >> 5) + 8 * q;
+      const bool ok = r.c * KC + k < B;
+      T w[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = ok ? (T)((double)r.v[q][t] - ob[t]) : (T)0;
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(&Pn.s[k][4 * m4]) = make_float4(w[0], w[1], w[2], w[3]);
+      } else {
+        *reinterpret_cast<double2 *>(&Pn.s[k][4 * m4]) = make_double2(w[0], w[1]);
+        *reinterpret_cast<double2 *>(&Pn.s[k][4 * m4 + 2]) = make_double2(w[2], w[3]);
+      }
+    }
+  }
+};
+
+// The pipelined K loop of Tile128 for loaders whose store needs the side.
+template <typename T, int KC, bool KM, class LD>
+__device__ __forceinline__ void run_sided(const LD &ld, int nchunks, Panel<T, KC, KM> &sA, Panel<T, KC, KM> &sB,
+                                          typename Tile128<T>::acc_t (&acc)[4][4]) {
+  typename LD::Regs ra, rb;
+  ld.load(ra, 0, false);
+  ld.load(rb, 0, true);
+  for (int c = 0; c < nchunks; ++c) {
+    ld.store(ra, sA, false);
+    ld.store(rb, sB, true);
     __syncthreads();
-    TT::template step<KC, KC + 1>(sA, sB, acc);
+    if (c + 1 < nchunks) {
+      ld.load(ra, c + 1, false);
+      ld.load(rb, c + 1, true);
+    }
+    Tile128<T>::template step<KC, KM>(sA, sB, acc);
     __syncthreads();
   }
+}
+
+// S[i][j] = (1/B) sum_b (O[b][i] - <O_i>)(O[b][j] - <O_j>) + eps [i == j],
+// lower 128 x 128 blocks (row stride ldS).  T = double: FP64 operands and
+// accumulation; T = float: the centred values are rounded to FP32 and
+// accumulated by the FP32 matrix cores.
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
+                                                   const double *__restrict__ obar, double eps,
+                                                   double *__restrict__ S, int64_t ldS, int ntiles) {
+  constexpr int KC = sizeof(T) == 4 ? 32 : 16;
+  __shared__ Panel<T, KC, true> sA, sB;
+  using TT = Tile128<T>;
+  int bi, bj;
+  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
+  const int64_t i0 = (int64_t)bi * 128, j0 = (int64_t)bj * 128;
+  const SyrkLoader<T, KC, VEC> ldr(O, ldO, B, P, i0, j0, obar);
+  typename TT::acc_t acc[4][4];
+  TT::zero(acc);
+  run_sided<T, KC, true>(ldr, (B + KC - 1) / KC, sA, sB, acc);
   const double inv = 1.0 / B;
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
@@ -213,38 +283,76 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = i0 + TT::row_of(tm, r), col = j0 + TT::col_of(tn);
-        if (row < P && col <= row) S[row * P + col] = (double)acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
+        if (row < P && col <= row) S[row * ldS + col] = (double)acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
       }
 }
 
-// Sample-space Gram: K[a][c] = (1/B) sum_k (O[a][k]-<O_k>)(O[c][k]-<O_k>) + eps [a == c].
+// Loader of the sample-space Gram tiles: panel rows are samples a0.. (A side)
+// or c0.. (B side), k runs over parameters in chunks of 16.  Samples past B
+// are clamped (outputs not stored); parameters past P are zeroed.
+template <bool VEC>
+struct GramLoader {
+  const float *O;
+  int64_t ldO;
+  int B;
+  int64_t P;
+  int a0, c0;
+  const double *obar;
+  struct Regs {
+    float v[2][4];
+    double ob[4];
+    int c;
+  };
+  __device__ __forceinline__ void load(Regs &r, int c, bool bside) const {
+    const int k4 = threadIdx.x & 3;
+    const int64_t k = (int64_t)c * 16 + 4 * k4;
+    r.c = c;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) r.ob[t] = obar[k + t < P ? k + t : P - 1];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int m = (threadIdx.x + 256 * q) >> 2;
+      const int a = (bside ? c0 : a0) + m;
+      const float *row = O + (int64_t)(a < B ? a : B - 1) * ldO;
+      if constexpr (VEC) {
+        const float4 x = *reinterpret_cast<const float4 *>(row + (k <= P - 4 ? k : P - 4));
+        r.v[q][0] = x.x; r.v[q][1] = x.y; r.v[q][2] = x.z; r.v[q][3] = x.w;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) r.v[q][t] = row[k + t < P ? k + t : P - 1];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(const Regs &r, Panel<double, 16, false> &Pn, bool) const {
+    const int k4 = threadIdx.x & 3;
+    const int64_t k = (int64_t)r.c * 16 + 4 * k4;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int m = (threadIdx.x + 256 * q) >> 2;
+      double w[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) w[t] = k + t < P ? (double)r.v[q][t] - r.ob[t] : 0.0;
+      *reinterpret_cast<double2 *>(&Pn.s[m][4 * k4]) = make_double2(w[0], w[1]);
+      *reinterpret_cast<double2 *>(&Pn.s[m][4 * k4 + 2]) = make_double2(w[2], w[3]);
+    }
+  }
+};
+
+// Sample-space Gram: K[a][c] = (1/B) sum_k (O[a][k]-<O_k>)(O[c][k]-<O_k>) + eps [a == c]
+// (row stride ldK).
+template <bool VEC>
 __global__ __launch_bounds__(256, 2) void gram_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
                                                    const double *__restrict__ obar, double eps,
-                                                   double *__restrict__ K) {
-  constexpr int KC = 32;
-  __shared__ double sA[128][KC + 1];
-  __shared__ double sB[128][KC + 1];
+                                                   double *__restrict__ K, int64_t ldK, int ntiles) {
+  __shared__ Panel<double, 16, false> sA, sB;
   using TT = Tile128<double>;
   int bi, bj;
-  lower_block(blockIdx.x, bi, bj);
+  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
   const int a0 = bi * 128, c0 = bj * 128;
-  const int lk = threadIdx.x & (KC - 1), lr = threadIdx.x / KC;  // 8 rows per pass
+  const GramLoader<VEC> ldr{O, ldO, B, P, a0, c0, obar};
   TT::acc_t acc[4][4];
   TT::zero(acc);
-  for (int64_t kb = 0; kb < P; kb += KC) {
-    const int64_t k = kb + lk;
-    const double ob = k < P ? obar[k] : 0.0;
-#pragma unroll 4
-    for (int q = 0; q < 128 / 8; ++q) {
-      const int r = lr + 8 * q;
-      const int ra = a0 + r, rc = c0 + r;
-      sA[r][lk] = (ra < B && k < P) ? (double)O[(int64_t)ra * ldO + k] - ob : 0.0;
-      sB[r][lk] = (rc < B && k < P) ? (double)O[(int64_t)rc * ldO + k] - ob : 0.0;
-    }
-    __syncthreads();
-    TT::step<KC, KC + 1>(sA, sB, acc);
-    __syncthreads();
-  }
+  run_sided<double, 16, false>(ldr, (int)((P + 15) / 16), sA, sB, acc);
   const double inv = 1.0 / B;
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
@@ -253,7 +361,7 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const float *__restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = a0 + TT::row_of(tm, r), col = c0 + TT::col_of(tn);
-        if (row < B && col <= row) K[(int64_t)row * B + col] = acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
+        if (row < B && col <= row) K[(int64_t)row * ldK + col] = acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
       }
 }
 
@@ -400,11 +508,14 @@ __global__ void scale_copy_kernel(const double *__restrict__ a, int64_t n, doubl
 
 static size_t al(size_t bytes) { return (bytes + 255) / 256 * 256; }
 
+// row stride of the explicit matrices: even, so that rows are 16-byte aligned
+static int64_t ld_even(int64_t n) { return (n + 1) & ~(int64_t)1; }
+
 struct SrPlan {
   int method;
   int nch, rows_per_chunk;
   int npq;
-  size_t off_scal, off_status, off_ec, off_obar, off_F, off_pa, off_pb, off_M, off_rhs, off_r, off_p, off_q,
+  size_t off_scal, off_status, off_ec, off_obar, off_F, off_pa, off_pb, off_M, off_r, off_p, off_q,
       off_u, off_pq, off_alpha, off_chol, total;
 };
 
@@ -432,8 +543,7 @@ static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
   s.off_pa = take((size_t)s.nch * P * 8);
   s.off_pb = take((size_t)s.nch * P * 8);
   if (s.method == 1) {
-    s.off_M = take((size_t)P * P * 8);
-    s.off_rhs = take((size_t)P * 8);
+    s.off_M = take((size_t)(P + 1) * ld_even(P) * 8);  // last row: right-hand side
     s.off_chol = take(chol_workspace_bytes(P));
   } else if (s.method == 2) {
     s.off_r = take((size_t)P * 8);
@@ -442,8 +552,7 @@ static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
     s.off_u = take((size_t)B * 8);
     s.off_pq = take((size_t)s.npq * 8);
   } else {
-    s.off_M = take((size_t)B * B * 8);
-    s.off_rhs = take((size_t)B * 8);
+    s.off_M = take((size_t)(B + 1) * ld_even(B) * 8);
     s.off_alpha = take((size_t)B * 8);
     s.off_chol = take(chol_workspace_bytes(B));
   }
@@ -485,6 +594,8 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
   double *pb = reinterpret_cast<double *>(ws + pl.off_pb);
   // 16-byte loads of O when every row starts 16-byte aligned
   const bool vec = (reinterpret_cast<uintptr_t>(O) % 16 == 0) && (ldO % 4 == 0);
+  // 16-byte loads in the tiled S / Gram kernels also need whole groups of 4 columns
+  const bool tvec = vec && (P % 4 == 0);
   // <E>, Var E, E^c (and the Cholesky status cleared); <O>, F
   energy_stats_kernel<<<1, 1024, 0, st>>>(e_loc, B, ec, scal, status);
   const dim3 cgrid((unsigned)((P + 255) / 256), (unsigned)pl.nch);
@@ -500,24 +611,28 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
   vqmc_status rc = VQMC_OK;
   if (pl.method == 1) {
     double *S = reinterpret_cast<double *>(ws + pl.off_M);
-    const int64_t T = (P + 127) / 128;
-    if (o->s_prec == 1)
-      syrk_kernel<double><<<(unsigned)(T * (T + 1) / 2), 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S);
-    else
-      syrk_kernel<float><<<(unsigned)(T * (T + 1) / 2), 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S);
+    const int64_t T = (P + 127) / 128, ldS = ld_even(P);
+    const int nt = (int)(T * (T + 1) / 2);
+    if (o->s_prec == 1) {
+      if (tvec) syrk_kernel<double, true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      else syrk_kernel<double, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+    } else {
+      if (tvec) syrk_kernel<float, true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      else syrk_kernel<float, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+    }
     VQMC_LAUNCH_CHECK();
-    double *rhs = reinterpret_cast<double *>(ws + pl.off_rhs);
-    scale_copy_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(Fv, P, 1.0, rhs);
-    rc = chol_factor_solve(S, P, rhs, delta, ws + pl.off_chol, status, st);
+    scale_copy_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(Fv, P, 1.0, S + P * ldS);
+    rc = chol_factor_solve(S, P, ldS, delta, ws + pl.off_chol, status, st);
   } else if (pl.method == 3) {
     double *K = reinterpret_cast<double *>(ws + pl.off_M);
     double *alpha = reinterpret_cast<double *>(ws + pl.off_alpha);
-    const int64_t T = (B + 127) / 128;
-    gram_kernel<<<(unsigned)(T * (T + 1) / 2), 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K);
-    double *rhs = reinterpret_cast<double *>(ws + pl.off_rhs);
-    scale_copy_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ec, B, 1.0 / B, rhs);
+    const int64_t T = (B + 127) / 128, ldK = ld_even(B);
+    const int nt = (int)(T * (T + 1) / 2);
+    if (tvec) gram_kernel<true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
+    else gram_kernel<false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
+    scale_copy_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ec, B, 1.0 / B, K + B * ldK);
     VQMC_LAUNCH_CHECK();
-    rc = chol_factor_solve(K, B, rhs, alpha, ws + pl.off_chol, status, st);
+    rc = chol_factor_solve(K, B, ldK, alpha, ws + pl.off_chol, status, st);
     if (rc == VQMC_OK) {
       if (vec)
         col_partial4_kernel<true><<<cgrid4, 256, 0, st>>>(O, ldO, B, P, obar, alpha, nullptr, pl.rows_per_chunk,

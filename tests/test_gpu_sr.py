@@ -21,7 +21,10 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-CASES = [(300, 200), (200, 517), (64, 64), (97, 1)]
+# sizes span partial 64-blocks, odd orders (unaligned rows, scalar loads),
+# several 256-column outer panels, an order that is a multiple of 128 (the
+# right-hand side row then opens a block row of its own) and of 256
+CASES = [(300, 200), (200, 517), (64, 64), (97, 1), (130, 384), (256, 512), (515, 300), (777, 1030)]
 
 
 @pytest.mark.parametrize("B,P", CASES)
