@@ -11,7 +11,13 @@
  * launch and return VQMC_ERR_ARG / VQMC_ERR_SHAPE with no side effect; a
  * failed launch returns VQMC_ERR_DEVICE; faults inside kernels surface at the
  * caller's next synchronisation.  Calls on different streams that write the
- * same buffers race; the library keeps no state between calls.
+ * same buffers race.  The library keeps no data between calls; the one
+ * resource it holds is, per device, an internal HIP stream and two events
+ * (created by the first Cholesky solve of order > 512 and kept until the
+ * process ends) on which that solve overlaps part of its trailing updates
+ * with the factorisation of the next panel; the call's own stream waits for
+ * that work before the call's remaining kernels, so the call still behaves
+ * as work enqueued on its own stream.
  *
  * Layouts (a specification the FP64 test oracle also follows):
  *   - site i = y*L + x, periodic boundaries, spin +1 = up, -1 = down (Sec. 2.1);

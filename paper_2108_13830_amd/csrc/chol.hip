@@ -24,6 +24,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "chol.hpp"
@@ -311,18 +312,32 @@ struct TrailLoader {
   }
 };
 
-// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = 256): lower
-// 128 x 128 tiles of rows [p1, nr) and columns [p1, n),
-// M[r][c] -= sum_{t in [p0,p1)} L[r][t] L[c][t].
+// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = 256): 128 x 128
+// tiles of rows [p1, nr) and columns [p1, n) on or below the diagonal,
+// M[r][c] -= sum_{t in [p0,p1)} L[r][t] L[c][t].  Tile (bi, bj) counts block
+// rows and columns from p1.  ncb > 0: only the block columns bj < ncb (the
+// next outer panel), tile t = (t / ncb, t % ncb); ncb == 0: the lower
+// triangle of block rows and columns >= 2 (the rest).
 __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restrict__ M, int64_t n, int64_t nr,
-                                                            int64_t ld, int64_t p0, int64_t p1, int ntiles) {
+                                                            int64_t ld, int64_t p0, int64_t p1, int ntiles,
+                                                            int ncb) {
   constexpr int KC = 16;
   __shared__ Panel<double, KC, false> sA, sB;
   using TT = Tile128<double>;
   int bi, bj;
-  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
+  const int t = xcd_contiguous(blockIdx.x, ntiles);
+  if (ncb > 0) {
+    bi = t / ncb;
+    bj = t - bi * ncb;
+  } else {
+    lower_block(t, bi, bj);
+    bi += 2;
+    bj += 2;
+  }
   const int64_t r0 = p1 + (int64_t)bi * 128, c0 = p1 + (int64_t)bj * 128;
-  if (c0 >= n) return;  // the extra block row of the augmented matrix has no diagonal tile
+  // tiles above the diagonal, and the extra block row of the augmented matrix
+  // past the last column (uniform per workgroup)
+  if (bj > bi || c0 >= n) return;
   TrailLoader<KC> ldr{M, ld, nr, r0, c0, p0};
   TT::acc_t acc[4][4];
   TT::zero(acc);
@@ -433,10 +448,44 @@ size_t chol_workspace_bytes(int64_t n) {
   return (size_t)nb * CB * CB * 8;
 }
 
+// A second stream and two events per device, created on first use and kept
+// for the life of the process: the trailing update of the columns past the
+// next outer panel runs there, concurrently with the factorisation of that
+// panel.  A factorisation holds the device's lock while it enqueues, so that
+// calls from several host threads pair their event records and waits.
+namespace {
+struct Side {
+  bool tried = false, ok = false;
+  hipStream_t s = nullptr;
+  hipEvent_t next = nullptr, rest = nullptr;
+  std::mutex mu;
+};
+std::mutex side_mu;
+Side side_tab[64];
+
+Side *side_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(side_mu);
+  Side &sd = side_tab[dev];
+  if (!sd.tried) {
+    sd.tried = true;
+    sd.ok = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&sd.next, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&sd.rest, hipEventDisableTiming) == hipSuccess;
+  }
+  return sd.ok ? &sd : nullptr;
+}
+}  // namespace
+
 vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void *ws, int *status, hipStream_t st) {
   if (n < 1 || ld < n || (ld & 1) || (reinterpret_cast<uintptr_t>(M) & 15)) return VQMC_ERR_ARG;
   double *Linv = reinterpret_cast<double *>(ws);
   const int64_t nr = n + 1;  // rows of the augmented matrix; row n carries the right-hand side
+  Side *sd = n > 2 * OB ? side_for_current_device() : nullptr;
+  std::unique_lock<std::mutex> hold;
+  if (sd) hold = std::unique_lock<std::mutex>(sd->mu);
+  bool rest_pending = false;
   for (int64_t p0 = 0; p0 < n; p0 += OB) {
     const int64_t p1 = (p0 + OB) < n ? p0 + OB : n;
     for (int64_t c0 = p0; c0 < p1; c0 += CB) {
@@ -454,12 +503,26 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
         chol_panel_update_kernel<<<g, 256, 0, st>>>(M, nr, ld, c0, p1);
       }
     }
-    if (p1 < n) {
-      const int64_t T = (nr - p1 + 127) / 128;
-      const int nt = (int)(T * (T + 1) / 2);
-      chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt);
+    if (p1 >= n) break;
+    const int T = (int)((nr - p1 + 127) / 128);
+    const int ncb = T < 2 ? T : 2;  // block columns of the next outer panel
+    // the next panel's columns must also have the previous rest update
+    if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
+    chol_trailing_kernel<<<(unsigned)(T * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, T * ncb, ncb);
+    if (T > 2) {
+      const int nt = (T - 2) * (T - 1) / 2;
+      if (sd) {
+        if (hipEventRecord(sd->next, st) != hipSuccess || hipStreamWaitEvent(sd->s, sd->next, 0) != hipSuccess)
+          return VQMC_ERR_DEVICE;
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, sd->s>>>(M, n, nr, ld, p0, p1, nt, 0);
+        if (hipEventRecord(sd->rest, sd->s) != hipSuccess) return VQMC_ERR_DEVICE;
+        rest_pending = true;
+      } else {
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt, 0);
+      }
     }
   }
+  if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
   // row n now holds y = L^-1 rhs; L^T x = y from the last block (y is consumed)
   double *y = M + n * ld;
