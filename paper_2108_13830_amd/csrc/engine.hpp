@@ -265,6 +265,127 @@ struct Engine {
     }
   }
 
+  // Neighbour table of the implicit GEMM, built once per kernel:
+  // nbt[tap][r] = row of site (y + tap/3 - 1, x + tap%3 - 1) (periodic) of
+  // the configuration of row r = g*N + y*L + x; rows past G*N use the last
+  // row.  It replaces the per-K-step index arithmetic of the gather.
+  static constexpr int NBT_ELEMS = 9 * MAXROWS;
+  __device__ static __forceinline__ void build_nbt(uint16_t *nbt, int G, int L, int N) {
+    const int Rf = G * N;
+    for (int idx = threadIdx.x; idx < NBT_ELEMS; idx += NTHR) {
+      const int tap = idx / MAXROWS, r0 = idx - tap * MAXROWS;
+      const int r = r0 < Rf ? r0 : Rf - 1;
+      const int g = r / N, site = r - g * N, y = site / L, x = site - y * L;
+      nbt[idx] = (uint16_t)(g * N + wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L));
+    }
+  }
+
+  // Lift layer on the FP32 matrix cores: K = 9 taps padded to 12,
+  // A[row][tap] = s[nb(row, tap)] (exact +-1), B[tap][co] = W0[co][tap].
+  __device__ static __forceinline__ void lift_tab(const float *__restrict__ theta, const int8_t *sp,
+                                                  const uint16_t *nbt, int R, char *act) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float *W0 = theta;
+    f32x4 acc[TPW][NT];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int k = 4 * s + (lane >> 4);
+      const bool kv = k < 9;
+      const int kk = kv ? k : 0;
+      float b[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + (lane & 15);
+        const float w = W0[(n < C ? n : C - 1) * 9 + kk];
+        b[nt] = (kv && n < C) ? w : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int row = (wave + i * NW) * 16 + (lane & 15);
+        const float a = (float)sp[nbt[kk * MAXROWS + row]];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(kv ? a : 0.f, b[nt], acc[i][nt]);
+      }
+    }
+    write_tiles(acc, theta + 9 * C, R, act, nullptr);
+  }
+
+  // K loop of one C -> C layer over the wave's row tiles with the gather
+  // rows read from the neighbour table; results stay in acc.
+  __device__ static __forceinline__ void kloop_tab(const char *act, const char *frag, const uint16_t *nbt,
+                                                   f32x4 (&acc)[TPW][NT]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int rowi[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) rowi[i] = (wave + i * NW) * 16 + (lane & 15);
+    if constexpr (F32) {
+      // A: act[nb][4 c4 + lane/16]; the four K-steps of a tap use the same
+      // gather row, at immediate offsets
+      const float *actf = reinterpret_cast<const float *>(act) + (lane >> 4);
+      const float *fragf = reinterpret_cast<const float *>(frag) + lane;
+      constexpr int SPT = C / 4;
+#pragma unroll 3
+      for (int tap = 0; tap < 9; ++tap) {
+        int nb[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) nb[i] = (int)nbt[tap * MAXROWS + rowi[i]] * LDA;
+#pragma unroll
+        for (int c4 = 0; c4 < SPT; ++c4) {
+          const int s = tap * SPT + c4;
+          float b[NT], a[TPW];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i) a[i] = actf[nb[i] + 4 * c4];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a[i], b[nt], acc[i][nt]);
+        }
+      }
+    } else {
+      const uint16_t *hi = reinterpret_cast<const uint16_t *>(act);
+      for (int s = 0; s < KS; ++s) {
+        u16x8 bh[NT], bl[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag + (size_t)((s * NT + nt) * 64 + lane) * FRAG);
+          bh[nt] = f[0];
+          if constexpr (X3) bl[nt] = f[1];
+        }
+        const int k0 = 32 * s + 8 * (lane >> 4);
+        const bool kv = k0 < 9 * C;
+        // lanes whose K slice lies past 9C read a valid row and multiply zero weights
+        const int tap = kv ? k0 / C : 0, ci0 = kv ? k0 - tap * C : 0;
+        u16x8 ah[TPW], al[TPW];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int nb = nbt[tap * MAXROWS + rowi[i]];
+          ah[i] = *reinterpret_cast<const u16x8 *>(hi + phys(nb, ci0));
+          if constexpr (X3) al[i] = *reinterpret_cast<const u16x8 *>(hi + MAXROWS * C + phys(nb, ci0));
+        }
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[i][nt] = mma_bf16(ah[i], bh[nt], acc[i][nt]);
+            if constexpr (X3) {
+              acc[i][nt] = mma_bf16(ah[i], bl[nt], acc[i][nt]);
+              acc[i][nt] = mma_bf16(al[i], bh[nt], acc[i][nt]);
+            }
+          }
+      }
+    }
+  }
+
   // Writes tanh(acc + bias) of the wave's tiles into the activation buffer
   // (and, when scratch != nullptr, into scratch[row][co] in global memory).
   __device__ static __forceinline__ void write_tiles(const f32x4 (&acc)[TPW][NT], const float *bias,
@@ -311,17 +432,19 @@ struct Engine {
   }
 
   // Full forward pass of G configurations sp[G][N] (LDS) -> lp[G] (LDS,
-  // FP64).  smem_act / smem_frag are this engine's LDS regions.  Begins and
-  // ends with the block synchronised.
+  // FP64).  smem_act / smem_frag are this engine's LDS regions; nbt is the
+  // neighbour table built by build_nbt for at least G configurations.
+  // Begins and ends with the block synchronised.
   __device__ static __forceinline__ void forward(const float *__restrict__ theta, int n_layers, const int8_t *sp,
-                                 int G, int L, int N, char *smem_act, char *smem_frag, double *lp) {
+                                                 int G, int N, char *smem_act, char *smem_frag,
+                                                 const uint16_t *nbt, double *lp) {
     const int R = G * N;
-    lift(theta, sp, R, L, N, smem_act);
     stage_weights(theta + layer_offset(C, 1), smem_frag);
+    lift_tab(theta, sp, nbt, R, smem_act);
     __syncthreads();
     for (int l = 1; l <= n_layers; ++l) {
       f32x4 acc[TPW][NT];
-      kloop<false, 1>(smem_act, smem_frag, R, L, N, acc);
+      kloop_tab(smem_act, smem_frag, nbt, acc);
       __syncthreads();
       const float *bias = theta + layer_offset(C, l) + 9 * C * C;
       if (l < n_layers) {

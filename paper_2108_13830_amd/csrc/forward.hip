@@ -94,7 +94,7 @@ __device__ __forceinline__ void philox(uint32_t &c0, uint32_t &c1, uint32_t &c2,
 // ------------------------------------------------------------- log |psi|
 
 template <int C, int PREC, int NW, int TPW>
-__global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void logpsi_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void logpsi_kernel(const float *__restrict__ theta,
                                                          const int8_t *__restrict__ spins, int B,
                                                          int L, int n_layers, int marshall, int G,
                                                          double *__restrict__ out,
@@ -103,13 +103,15 @@ __global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void l
   __shared__ __align__(16) char s_act[E::ACT_BYTES];
   __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
   __shared__ int8_t s_sp[E::MAXROWS];
+  __shared__ uint16_t s_nbt[E::NBT_ELEMS];
   __shared__ double s_lp[64];
   const int N = L * L;
+  E::build_nbt(s_nbt, G, L, N);
   for (int base = blockIdx.x * G; base < B; base += gridDim.x * G) {
     const int Gb = min(G, B - base);
     for (int idx = threadIdx.x; idx < Gb * N; idx += E::NTHR) s_sp[idx] = spins[(size_t)base * N + idx];
     __syncthreads();
-    E::forward(theta, n_layers, s_sp, Gb, L, N, s_act, s_frag, s_lp);
+    E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
     for (int g = threadIdx.x; g < Gb; g += E::NTHR) {
       out[base + g] = s_lp[g];
       if (sign) {
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void l
 // engine in batches of G, and the off-diagonal terms J/2 mu exp(dlog) are
 // accumulated in FP64 in bond order.
 template <int C, int PREC, int NW, int TPW>
-__global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void eloc_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const float *__restrict__ theta,
                                                        const int8_t *__restrict__ spins, int B, int L,
                                                        int n_layers, double J1, double J2,
                                                        int marshall, int G,
@@ -150,8 +152,10 @@ __global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void e
   __shared__ double s_terms[64];
   __shared__ double s_red[NW];
   __shared__ int s_ired[NW];
+  __shared__ uint16_t s_nbt[E::NBT_ELEMS];
   const int tid = threadIdx.x;
   const int N = L * L, NB = 4 * N;
+  E::build_nbt(s_nbt, G, L, N);
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const int8_t *s = spins + (size_t)b * N;
     int sz = 0, bad = 0;
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(NW * 64, (C <= 16 && PREC == P_F32) ? 2 : 1) void e
         s_sp[idx] = v;
       }
       __syncthreads();
-      E::forward(theta, n_layers, s_sp, Gb, L, N, s_act, s_frag, s_lp);
+      E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
       if (q0 == 0) lp0 = s_lp[0];
       for (int g = tid; g < Gb; g += E::NTHR) {
         const int q = q0 + g;
@@ -244,13 +248,15 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
   __shared__ double s_lp[64];
   __shared__ int s_ired[NW];
   __shared__ int s_pick[2];
+  __shared__ uint16_t s_nbt[E::NBT_ELEMS];
   const int tid = threadIdx.x;
   const int N = L * L;
   const int b = blockIdx.x;
   int8_t *s = spins + (size_t)b * N;
+  E::build_nbt(s_nbt, 1, L, N);
   for (int i = tid; i < N; i += E::NTHR) s_sp[i] = s[i];
   __syncthreads();
-  E::forward(theta, n_layers, s_sp, 1, L, N, s_act, s_frag, s_lp);
+  E::forward(theta, n_layers, s_sp, 1, N, s_act, s_frag, s_nbt, s_lp);
   double lp = s_lp[0];
   int acc = 0;
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
       s_sp[j] = v;
     }
     __syncthreads();
-    E::forward(theta, n_layers, s_sp, 1, L, N, s_act, s_frag, s_lp);
+    E::forward(theta, n_layers, s_sp, 1, N, s_act, s_frag, s_nbt, s_lp);
     const double lpn = s_lp[0];
     double hast = 0.0;
     if (proposal == 1) {
