@@ -136,26 +136,36 @@ struct LC {
 };
 
 // The engine's K loop over the first n tile slots only (n wave-uniform,
-// 0 <= n <= TPW), dispatched to a compile-time trip count.
+// 0 <= n <= TPW), dispatched to a compile-time trip count.  rows[i] is the
+// lattice site of the lane's output row in tile slot i.
 template <class EP, int TPW, int K = 1>
-__device__ __forceinline__ void kloop_n(int n, const char *act, const char *frag, const int (&pk)[TPW], int L,
-                                        f32x4 (&acc)[TPW][EP::NT]) {
+__device__ __forceinline__ void kloop_n(int n, const char *act, const char *frag, const uint16_t *nbt,
+                                        const int (&rows)[TPW], f32x4 (&acc)[TPW][EP::NT]) {
   if constexpr (K <= TPW) {
     if (n <= K) {
-      EP::template kloop_pk<false, 1, K>(act, frag, pk, L, acc);
+      EP::template kloop_rows<K>(act, frag, nbt, rows, acc);
       return;
     }
-    kloop_n<EP, TPW, K + 1>(n, act, frag, pk, L, acc);
+    kloop_n<EP, TPW, K + 1>(n, act, frag, nbt, rows, acc);
   }
 }
 
-// Copies one layer's packed fragments (bytes, a multiple of 16) into LDS.
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Starts copying one layer's packed fragments (bytes, a multiple of 1 KiB)
+// into LDS with direct-to-LDS loads: no registers are involved and each wave
+// instruction moves 1 KiB.  The copy is complete once every thread has
+// passed wait_copies() and a barrier.
 template <int NTHR>
-__device__ __forceinline__ void stage(char *dst, const char *__restrict__ src, int bytes) {
-  const uint4 *s = reinterpret_cast<const uint4 *>(src);
-  uint4 *d = reinterpret_cast<uint4 *>(dst);
-  for (int i = threadIdx.x; i < bytes / 16; i += NTHR) d[i] = s[i];
+__device__ __forceinline__ void stage_async(char *dst, const char *__restrict__ src, int bytes) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < (bytes >> 10); c += NTHR / 64)
+    __builtin_amdgcn_global_load_lds(src + (size_t)c * 1024 + lane * 16, (lds_ptr_t)(dst + c * 1024), 16, 0, 0);
 }
+
+// Waits for this thread's outstanding memory operations (the direct-to-LDS
+// copies included).
+__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
 
 template <int C, int PREC, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restrict__ theta,
@@ -173,17 +183,24 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
   constexpr int MR = K::MR;
   __shared__ __align__(16) char s_act[K::ACT];
   __shared__ __align__(16) char s_frag[K::FRAG];
+  __shared__ uint16_t s_nbt[E32::NBT_ELEMS];
   __shared__ int8_t s_sig[MR];
   __shared__ int16_t s_bonds[4 * MR];
   __shared__ double s_red[NW];
   __shared__ int s_ired[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = L * L, NB = 4 * N;
-  const size_t per_frag32 = (size_t)E32::KS * NT * 64 * E32::FRAG;
-  const size_t per_fragp = (size_t)EP::KS * NT * 64 * EP::FRAG;
+  const int per_frag32 = E32::KS * NT * 64 * E32::FRAG;
+  const int per_fragp = EP::KS * NT * 64 * EP::FRAG;
+  static_assert((E32::KS * NT * 64 * E32::FRAG) % 1024 == 0 && (EP::KS * NT * 64 * EP::FRAG) % 1024 == 0,
+                "fragment blocks are copied in 1 KiB pieces");
   float *zsc = zscratch + (size_t)blockIdx.x * (n_layers + 1) * N * C;
+  // neighbour table of the single configuration: nbt[tap][site]
+  E32::build_nbt(s_nbt, 1, L, N);
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const int8_t *s = spins + (size_t)b * N;
+    // the first FP32 layer's fragments arrive while the bonds are scanned
+    stage_async<NW * 64>(s_frag, frag32, per_frag32);
     int sz = 0, bad = 0;
     for (int i = tid; i < N; i += NW * 64) {
       const int8_t v = s[i];
@@ -219,21 +236,21 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
       const float *W0 = theta, *b0 = theta + 9 * C;
       for (int idx = tid; idx < N * C; idx += NW * 64) {
         const int row = idx / C, co = idx - row * C;
-        const int y = row / L, x = row - y * L;
         float z = b0[co];
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap)
-          z += W0[co * 9 + tap] * (float)s_sig[wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L)];
+        for (int tap = 0; tap < 9; ++tap) z += W0[co * 9 + tap] * (float)s_sig[s_nbt[tap * MR + row]];
         zsc[idx] = z;
         E32::store_act(s_act, row, co, tanh_f(z));
       }
-      stage<NW * 64>(s_frag, frag32, (int)per_frag32);
+      wait_copies();
       __syncthreads();
       for (int l = 1; l <= n_layers; ++l) {
         f32x4 acc[TPW][NT];
-        E32::template kloop<false, 1>(s_act, s_frag, N, L, N, acc);
+        E32::kloop_tab(s_act, s_frag, s_nbt, acc);
         __syncthreads();
-        if (l < n_layers) stage<NW * 64>(s_frag, frag32 + (size_t)l * per_frag32, (int)per_frag32);
+        // next: the following FP32 layer, or the first layer of the s' pass
+        if (l < n_layers) stage_async<NW * 64>(s_frag, frag32 + (size_t)l * per_frag32, per_frag32);
+        else stage_async<NW * 64>(s_frag, fragp, per_fragp);
         const float *bias = theta + layer_offset(C, l) + 9 * C * C;
         float *zl = zsc + (size_t)l * N * C;
 #pragma unroll
@@ -252,11 +269,13 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
               }
             }
         }
+        wait_copies();
         __syncthreads();
       }
     }
 
-    // ---- every exchanged configuration, one at a time
+    // ---- every exchanged configuration, one at a time.  On entry to each
+    // s' the fragments of its first layer are in (or on their way to) LDS.
     double eacc = diag;
     bool finite = true;
     for (int q = 0; q < total; ++q) {
@@ -268,7 +287,6 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         uint4 *p = reinterpret_cast<uint4 *>(s_act);
         for (int idx = tid; idx < K::ACT / 16; idx += NW * 64) p[idx] = uint4{0, 0, 0, 0};
       }
-      stage<NW * 64>(s_frag, fragp, (int)per_fragp);
       __syncthreads();
       // lift: dz_1[x][c] = sum_tap W0[c][tap] ds[x + d(tap)] on the distance-1 box
       {
@@ -278,53 +296,51 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         for (int idx = tid; idx < R * C; idx += NW * 64) {
           const int r = idx / C, co = idx - r * C;
           const int site = bx.site(r, L);
-          const int y = site / L, x = site - y * L;
           float dz = 0.f;
 #pragma unroll
           for (int tap = 0; tap < 9; ++tap) {
-            const int nb = wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L);
+            const int nb = s_nbt[tap * MR + site];
             const float w = theta[co * 9 + tap];
             dz += nb == bi ? w * dsi : (nb == bj ? -w * dsi : 0.f);
           }
           EP::store_act(s_act, site, co, tanh_diff(zsc[site * C + co], dz));
         }
       }
+      wait_copies();
       __syncthreads();
       double part = 0.0;
       for (int l = 1; l <= n_layers; ++l) {
         Box bx;
         bx.set(y0, x0, ey, ex, l + 1, L);
         const int R = bx.H * bx.W;
-        int pk[TPW];
+        int rows[TPW];
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
           int r = (wave + i * NW) * 16 + (lane & 15);
           r = r < R ? r : R - 1;
-          const int site = bx.site(r, L), y = site / L;
-          pk[i] = (y << 5) | (site - y * L);
+          rows[i] = bx.site(r, L);
         }
-        f32x4 acc[TPW][NT];
         // tiles of this wave in the current box (wave-uniform)
         const int Ttot = (R + 15) / 16;
         const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
-        kloop_n<EP, TPW>(nti, s_act, s_frag, pk, L, acc);
-        __syncthreads();
-        if (l < n_layers) stage<NW * 64>(s_frag, fragp + (size_t)l * per_fragp, (int)per_fragp);
+        // the lane's output sites (four rows r0..r0+3 of each of its tiles,
+        // walking the box row-major; rows past the box reuse a valid site)
+        // and their pre-activations z_l(s), requested before the K loop so
+        // that the matrix work covers the memory latency
         const float *zl = zsc + (size_t)l * N * C;
+        int osite[TPW][4];
+        float za[TPW][4][NT];
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
-          const int T = wave + i * NW;
-          if (T * 16 < R) {
-            // the lane's four output rows r0..r0+3 walk the box row-major
-            const int r0 = T * 16 + (lane >> 4) * 4;
+          if (i < nti) {
+            const int r0 = (wave + i * NW) * 16 + (lane >> 4) * 4;
             int ry = r0 / bx.W, rx = r0 - ry * bx.W;
             int y = bx.ys + ry, x = bx.xs + rx;
             y = y < 0 ? y + L : (y >= L ? y - L : y);
             x = x < 0 ? x + L : (x >= L ? x - L : x);
-            int site[4];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-              site[jj] = y * L + x;
+              osite[i][jj] = y * L + x;
               ++rx;
               x = x + 1 == L ? 0 : x + 1;
               if (rx == bx.W) {
@@ -333,16 +349,25 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
                 y = y + 1 == L ? 0 : y + 1;
               }
             }
-            // all pre-activations of the tile first (in-bounds for every
-            // lane: rows past the box reuse a valid site), then the updates
-            float za[4][NT];
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
               for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + (lane & 15);
-                za[jj][nt] = zl[site[jj] * C + (co < C ? co : 0)];
+                za[i][jj][nt] = zl[osite[i][jj] * C + (co < C ? co : 0)];
               }
+          }
+        }
+        f32x4 acc[TPW][NT];
+        kloop_n<EP, TPW>(nti, s_act, s_frag, s_nbt, rows, acc);
+        __syncthreads();
+        // next layer's fragments (after the last layer: the first layer's,
+        // for the next s') arrive while this layer's differences are formed
+        stage_async<NW * 64>(s_frag, fragp + (size_t)(l < n_layers ? l : 0) * per_fragp, per_fragp);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          if (i < nti) {
+            const int r0 = (wave + i * NW) * 16 + (lane >> 4) * 4;
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
               if (r0 + jj < R) {
@@ -350,8 +375,8 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
                 for (int nt = 0; nt < NT; ++nt) {
                   const int co = nt * 16 + (lane & 15);
                   if (co < C) {
-                    const float dh = tanh_diff(za[jj][nt], acc[i][nt][jj]);
-                    if (l < n_layers) EP::store_act(s_act, site[jj], co, dh);
+                    const float dh = tanh_diff(za[i][jj][nt], acc[i][nt][jj]);
+                    if (l < n_layers) EP::store_act(s_act, osite[i][jj], co, dh);
                     else part += (double)dh;
                   }
                 }
@@ -359,6 +384,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
             }
           }
         }
+        if (l < n_layers) wait_copies();
         __syncthreads();
       }
       const double dlog = bsum<NW>(part, s_red);
@@ -368,6 +394,10 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
       finite = finite && isfinite(dlog);
       eacc += term;
     }
+    // the copy started by the last layer of the last s' must land before the
+    // next sample overwrites the buffer
+    wait_copies();
+    __syncthreads();
     if (tid == 0) {
       e_loc[b] = eacc;
       if (flags) flags[b] = ((!isfinite(eacc) || !finite) ? 1 : 0) | (sz != 0 ? 2 : 0) | (bad ? 4 : 0);
@@ -415,24 +445,30 @@ constexpr size_t frag_bytes_per_layer() {
 
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-int lc_tpw(int N) { return N <= 64 ? 1 : N <= 128 ? 2 : N <= 256 ? 4 : 9; }
+// Launch shapes by lattice size: (waves per workgroup, row tiles per wave),
+// with NW * TPW * 16 >= N rows for the dense pass of s.  Eight waves (two
+// per SIMD) from 16x16 up, so that one wave's memory and barrier waits are
+// covered by the other's matrix work.
+int lc_shape(int N) { return N <= 64 ? 0 : N <= 128 ? 1 : N <= 256 ? 2 : 3; }
 
-template <int C, int PREC, int TPW>
+template <int C, int PREC, int NW, int TPW>
 int lc_grid(int B) {
-  const int lds = LC<C, PREC, 4, TPW>::ACT + LC<C, PREC, 4, TPW>::FRAG + 5 * LC<C, PREC, 4, TPW>::MR + 256;
+  using K = LC<C, PREC, NW, TPW>;
+  const int lds = K::ACT + K::FRAG + 23 * K::MR + 256;
   int per_cu = 160 * 1024 / lds;
-  per_cu = per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu);
+  const int thr = 2048 / (NW * 64);
+  per_cu = per_cu < 1 ? 1 : (per_cu > thr ? thr : per_cu);
   const int g = 256 * per_cu;
   return B < g ? B : g;
 }
 
 template <int C, int PREC>
 int lc_grid_c(int N, int B) {
-  switch (lc_tpw(N)) {
-    case 1: return lc_grid<C, PREC, 1>(B);
-    case 2: return lc_grid<C, PREC, 2>(B);
-    case 4: return lc_grid<C, PREC, 4>(B);
-    default: return lc_grid<C, PREC, 9>(B);
+  switch (lc_shape(N)) {
+    case 0: return lc_grid<C, PREC, 4, 1>(B);
+    case 1: return lc_grid<C, PREC, 4, 2>(B);
+    case 2: return lc_grid<C, PREC, 8, 2>(B);
+    default: return lc_grid<C, PREC, 8, 5>(B);
   }
 }
 
@@ -444,7 +480,7 @@ size_t lc_ws(const vqmc_model *m, int B) {
          (size_t)grid * (n + 1) * N * C * 4;
 }
 
-template <int C, int PREC, int TPW>
+template <int C, int PREC, int NW, int TPW>
 vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
                       int32_t *flags, char *ws, hipStream_t st) {
   const int n = m->n_layers;
@@ -456,7 +492,7 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
   pack_lc_kernel<C, P_F32><<<(t32 + 255) / 256, 256, 0, st>>>(theta, n, f32);
   if (PREC != P_F32) pack_lc_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
   else fp = f32;
-  eloc_lc_kernel<C, PREC, 4, TPW><<<lc_grid<C, PREC, TPW>(B), 256, 0, st>>>(
+  eloc_lc_kernel<C, PREC, NW, TPW><<<lc_grid<C, PREC, NW, TPW>(B), NW * 64, 0, st>>>(
       theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags);
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
   return VQMC_OK;
@@ -465,11 +501,11 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
 template <int C, int PREC>
 vqmc_status lc_launch_c(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
                         int32_t *flags, char *ws, hipStream_t st) {
-  switch (lc_tpw(m->L * m->L)) {
-    case 1: return lc_launch<C, PREC, 1>(m, theta, spins, B, e_loc, flags, ws, st);
-    case 2: return lc_launch<C, PREC, 2>(m, theta, spins, B, e_loc, flags, ws, st);
-    case 4: return lc_launch<C, PREC, 4>(m, theta, spins, B, e_loc, flags, ws, st);
-    default: return lc_launch<C, PREC, 9>(m, theta, spins, B, e_loc, flags, ws, st);
+  switch (lc_shape(m->L * m->L)) {
+    case 0: return lc_launch<C, PREC, 4, 1>(m, theta, spins, B, e_loc, flags, ws, st);
+    case 1: return lc_launch<C, PREC, 4, 2>(m, theta, spins, B, e_loc, flags, ws, st);
+    case 2: return lc_launch<C, PREC, 8, 2>(m, theta, spins, B, e_loc, flags, ws, st);
+    default: return lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, ws, st);
   }
 }
 

@@ -319,13 +319,23 @@ struct Engine {
   __device__ static __forceinline__ void kloop_tab(const char *act, const char *frag, const uint16_t *nbt,
                                                    f32x4 (&acc)[TPW][NT]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int rowi[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) rowi[i] = (wave + i * NW) * 16 + (lane & 15);
+    kloop_rows<TPW>(act, frag, nbt, rowi, acc);
+  }
+
+  // The same K loop for tile i of this wave reading the lane's table column
+  // rowi[i] (the output row's own index into nbt); only the first NTILE tile
+  // slots are computed (compile time).
+  template <int NTILE>
+  __device__ static __forceinline__ void kloop_rows(const char *act, const char *frag, const uint16_t *nbt,
+                                                    const int (&rowi)[TPW], f32x4 (&acc)[TPW][NT]) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int i = 0; i < TPW; ++i)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    int rowi[TPW];
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) rowi[i] = (wave + i * NW) * 16 + (lane & 15);
     if constexpr (F32) {
       // A: act[nb][4 c4 + lane/16]; the four K-steps of a tap use the same
       // gather row, at immediate offsets
@@ -334,19 +344,19 @@ struct Engine {
       constexpr int SPT = C / 4;
 #pragma unroll 3
       for (int tap = 0; tap < 9; ++tap) {
-        int nb[TPW];
+        int nb[NTILE];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) nb[i] = (int)nbt[tap * MAXROWS + rowi[i]] * LDA;
+        for (int i = 0; i < NTILE; ++i) nb[i] = (int)nbt[tap * MAXROWS + rowi[i]] * LDA;
 #pragma unroll
         for (int c4 = 0; c4 < SPT; ++c4) {
           const int s = tap * SPT + c4;
-          float b[NT], a[TPW];
+          float b[NT], a[NTILE];
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64];
 #pragma unroll
-          for (int i = 0; i < TPW; ++i) a[i] = actf[nb[i] + 4 * c4];
+          for (int i = 0; i < NTILE; ++i) a[i] = actf[nb[i] + 4 * c4];
 #pragma unroll
-          for (int i = 0; i < TPW; ++i)
+          for (int i = 0; i < NTILE; ++i)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a[i], b[nt], acc[i][nt]);
         }
@@ -365,15 +375,15 @@ struct Engine {
         const bool kv = k0 < 9 * C;
         // lanes whose K slice lies past 9C read a valid row and multiply zero weights
         const int tap = kv ? k0 / C : 0, ci0 = kv ? k0 - tap * C : 0;
-        u16x8 ah[TPW], al[TPW];
+        u16x8 ah[NTILE], al[NTILE];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
+        for (int i = 0; i < NTILE; ++i) {
           const int nb = nbt[tap * MAXROWS + rowi[i]];
           ah[i] = *reinterpret_cast<const u16x8 *>(hi + phys(nb, ci0));
           if constexpr (X3) al[i] = *reinterpret_cast<const u16x8 *>(hi + MAXROWS * C + phys(nb, ci0));
         }
 #pragma unroll
-        for (int i = 0; i < TPW; ++i)
+        for (int i = 0; i < NTILE; ++i)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
             acc[i][nt] = mma_bf16(ah[i], bh[nt], acc[i][nt]);
