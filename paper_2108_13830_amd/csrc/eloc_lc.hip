@@ -72,17 +72,25 @@ __device__ __forceinline__ int bscan(int v, int *tmp, int *total) {
   return base + x - v;
 }
 
-// tanh of a small or large argument with relative accuracy: the odd series
-// below 0.1 (truncation < 1e-11 relative), the exponential form above.
-__device__ __forceinline__ float tanh_rel(float b) {
-  const float b2 = b * b;
-  if (fabsf(b) < 0.1f) return b * (1.f - b2 * (1.f / 3.f - b2 * (2.f / 15.f - b2 * (17.f / 315.f))));
-  return tanh_f(b);
-}
-
-// tanh(a + b) - tanh(a) with the relative accuracy of b.
+// tanh(a + b) - tanh(a) with the relative accuracy of b.  With
+// E_a = e^{2a} and E_c = e^{2(a+b)}:
+//   tanh(a + b) - tanh(a) = 2 (E_c - E_a) / ((E_c + 1)(E_a + 1)),
+// where E_c - E_a = E_a (e^{2b} - 1) is taken from the series of e^x - 1
+// (six terms) when |2b| < 0.25 (truncation below 5e-8 relative) and as the
+// plain difference otherwise (the two then differ by a factor e^{0.25} or
+// more, so the difference loses at most a factor 4.5 in relative accuracy).
+// Arguments are clamped to +-40 (e^80 < FLT_MAX; tanh is exactly +-1 in FP32
+// long before); a clamp only acts where both tanh values are saturated and
+// the result is 0 to FP32 precision either way.  Two exponentials and one
+// reciprocal.
 __device__ __forceinline__ float tanh_diff(float a, float b) {
-  return tanh_rel(b) * (1.f - tanh_f(a) * tanh_f(a + b));
+  const float ac = fminf(fmaxf(a, -40.f), 40.f), cc = fminf(fmaxf(a + b, -40.f), 40.f);
+  const float x = 2.f * b;
+  const float ea = __expf(2.f * ac), ec = __expf(2.f * cc);
+  const float em1 =
+      x * (1.f + x * (1.f / 2.f + x * (1.f / 6.f + x * (1.f / 24.f + x * (1.f / 120.f + x * (1.f / 720.f))))));
+  const float num = fabsf(x) < 0.25f ? ea * em1 : ec - ea;
+  return 2.f * num * __builtin_amdgcn_rcpf((ec + 1.f) * (ea + 1.f));
 }
 
 // Unwrapped bounding box of the exchanged pair of bond k: rows y0..y0+ey,
@@ -119,9 +127,17 @@ struct Box {
       xs = 0;
     }
   }
+  // lattice site of box row r (row-major over the box), without integer
+  // division: r / W from a float reciprocal with half-row margin
   __device__ __forceinline__ int site(int r, int L) const {
-    const int ry = r / W, rx = r - ry * W;
-    return (((ys + ry) % L + L) % L) * L + (((xs + rx) % L + L) % L);
+    const int ry = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)W));
+    const int rx = r - ry * W;
+    int y = ys + ry, x = xs + rx;
+    y += y < 0 ? L : 0;
+    y -= y >= L ? L : 0;
+    x += x < 0 ? L : 0;
+    x -= x >= L ? L : 0;
+    return y * L + x;
   }
 };
 

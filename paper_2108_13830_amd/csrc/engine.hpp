@@ -87,11 +87,17 @@ struct Engine {
   static_assert(F32 ? (C % 4 == 0) : (C % 8 == 0), "channel count not supported");
   static_assert(MAXROWS * C * 4 <= ACT_BYTES, "the head reuses the activation buffer");
 
-  // BF16 activation planes: 8-element groups XOR-swizzled by the row so that
-  // the 16 rows of a tile spread over the LDS banks.
+  // BF16 activation planes: rows of 2C bytes, 128/C of them per 256-byte
+  // span of the 64 LDS banks.  The 8-element (16-byte) groups of a row are
+  // XOR-swizzled by the row's span index, so that the 16 consecutive rows of
+  // a tile, read 16 bytes each, fall on 16 distinct 4-bank groups.
   __device__ static __forceinline__ int phys(int row, int c) {
-    if constexpr (C >= 16) return row * C + ((((c >> 3) ^ (row & (C / 8 - 1))) << 3) | (c & 7));
-    else return row * C + c;
+    if constexpr (C >= 16) {
+      constexpr int RSH = C == 16 ? 3 : 2;  // log2(128 / C)
+      return row * C + ((((c >> 3) ^ ((row >> RSH) & (C / 8 - 1))) << 3) | (c & 7));
+    } else {
+      return row * C + c;
+    }
   }
 
   __device__ static __forceinline__ void store_act(char *act, int row, int c, float h) {
