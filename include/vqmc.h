@@ -13,7 +13,7 @@
  * caller's next synchronisation.  Calls on different streams that write the
  * same buffers race.  The library keeps no data between calls; the one
  * resource it holds is, per device, an internal HIP stream and two events
- * (created by the first Cholesky solve of order > 512 and kept until the
+ * (created by the first Cholesky solve of order > 1024 and kept until the
  * process ends) on which that solve overlaps part of its trailing updates
  * with the factorisation of the next panel; the call's own stream waits for
  * that work before the call's remaining kernels, so the call still behaves

@@ -3,12 +3,12 @@
 // (Sec. 3.2.2: the Cholesky factor followed by forward and back substitution
 // instead of an explicit inverse of M).
 //
-// Right-looking, two block levels: 256-column outer panels, each factored as
-// four 64-column sub-panels.  Per sub-panel: one workgroup factors the 64 x 64
+// Right-looking, two block levels: 512-column outer panels, each factored as
+// eight 64-column sub-panels.  Per sub-panel: one workgroup factors the 64 x 64
 // diagonal block and, in the same sweep, inverts its triangle; the rows below
 // are then one GEMM with that small inverse; the rest of the outer panel is
-// updated.  After each outer panel the trailing matrix receives one rank-256
-// update on the FP64 matrix cores, so it is read and written once per 256
+// updated.  After each outer panel the trailing matrix receives one rank-512
+// update on the FP64 matrix cores, so it is read and written once per 512
 // columns.
 //
 // The right-hand side rides along as an extra last row of the matrix: the
@@ -36,7 +36,7 @@ namespace vqmc {
 namespace {
 
 constexpr int CB = 64;   // diagonal block / sub-panel width
-constexpr int OB = 256;  // outer panel width
+constexpr int OB = 512;  // outer panel width
 constexpr int SB = 256;  // block of the triangular solves
 
 __device__ __forceinline__ f64x4 mma64(double a, double b, f64x4 c) {
@@ -312,12 +312,12 @@ struct TrailLoader {
   }
 };
 
-// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = 256): 128 x 128
+// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = OB): 128 x 128
 // tiles of rows [p1, nr) and columns [p1, n) on or below the diagonal,
 // M[r][c] -= sum_{t in [p0,p1)} L[r][t] L[c][t].  Tile (bi, bj) counts block
 // rows and columns from p1.  ncb > 0: only the block columns bj < ncb (the
 // next outer panel), tile t = (t / ncb, t % ncb); ncb == 0: the lower
-// triangle of block rows and columns >= 2 (the rest).
+// triangle of block rows and columns >= OB / 128 (the rest).
 __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restrict__ M, int64_t n, int64_t nr,
                                                             int64_t ld, int64_t p0, int64_t p1, int ntiles,
                                                             int ncb) {
@@ -331,8 +331,8 @@ __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restric
     bj = t - bi * ncb;
   } else {
     lower_block(t, bi, bj);
-    bi += 2;
-    bj += 2;
+    bi += OB / 128;
+    bj += OB / 128;
   }
   const int64_t r0 = p1 + (int64_t)bi * 128, c0 = p1 + (int64_t)bj * 128;
   // tiles above the diagonal, and the extra block row of the augmented matrix
@@ -505,12 +505,12 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
     }
     if (p1 >= n) break;
     const int T = (int)((nr - p1 + 127) / 128);
-    const int ncb = T < 2 ? T : 2;  // block columns of the next outer panel
+    const int ncb = T < OB / 128 ? T : OB / 128;  // block columns of the next outer panel
     // the next panel's columns must also have the previous rest update
     if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
     chol_trailing_kernel<<<(unsigned)(T * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, T * ncb, ncb);
-    if (T > 2) {
-      const int nt = (T - 2) * (T - 1) / 2;
+    if (T > ncb) {
+      const int nt = (T - ncb) * (T - ncb + 1) / 2;
       if (sd) {
         if (hipEventRecord(sd->next, st) != hipSuccess || hipStreamWaitEvent(sd->s, sd->next, 0) != hipSuccess)
           return VQMC_ERR_DEVICE;

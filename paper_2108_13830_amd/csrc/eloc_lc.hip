@@ -89,7 +89,10 @@ __device__ __forceinline__ float tanh_diff(float a, float b) {
   const float ea = __expf(2.f * ac), ec = __expf(2.f * cc);
   const float em1 =
       x * (1.f + x * (1.f / 2.f + x * (1.f / 6.f + x * (1.f / 24.f + x * (1.f / 120.f + x * (1.f / 720.f))))));
-  const float num = fabsf(x) < 0.25f ? ea * em1 : ec - ea;
+  // both candidates are formed and one is picked bitwise (no branch)
+  const int sel = -(int)(fabsf(x) < 0.25f);
+  const int u = __float_as_int(ea * em1), t = __float_as_int(ec - ea);
+  const float num = __int_as_float(t ^ ((t ^ u) & sel));
   return 2.f * num * __builtin_amdgcn_rcpf((ec + 1.f) * (ea + 1.f));
 }
 

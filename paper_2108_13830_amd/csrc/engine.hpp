@@ -369,6 +369,9 @@ struct Engine {
       }
     } else {
       const uint16_t *hi = reinterpret_cast<const uint16_t *>(act);
+      // fully unrolled: the table and activation reads of step s+1 can be
+      // issued while the matrix instructions of step s run
+#pragma unroll
       for (int s = 0; s < KS; ++s) {
         u16x8 bh[NT], bl[NT];
 #pragma unroll
