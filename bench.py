@@ -144,6 +144,59 @@ def copy_calibration(mib):
                                            "bytes_out": nel * 4, "launches": 3}}), flush=True)
 
 
+def other_workload(V, torch, name, convs):
+    """One full step of another workload (uniform Sz = 0 configurations) per
+    convolution form: samples/s and stage times, for the second lattice the
+    metric names.  One warm-up step, one timed step per form."""
+    from vqmc_inputs import init_theta, uniform_sz0
+    wl = WORKLOADS[name]
+    L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
+    dev = torch.device("cuda:0")
+    th = torch.from_numpy(init_theta(C, n, seed=0)).to(dev)
+    spins = torch.from_numpy(uniform_sz0(L, B, seed=1)).to(dev)
+    spins_np = spins.cpu().numpy()
+    res = {"workload": "%s periodic J1-J2 (J2/J1=0.5), C=%d, n=%d, B=%d uniform Sz=0 configurations; "
+                       "E_loc (light cone) + O_k + SR (CG, tol 1e-8, at most 200 iterations)" % (name, C, n, B)}
+    base = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_FP32, V.ELOC_AUTO)
+    P = V.num_params(base)
+    O = torch.empty((B, P), dtype=torch.float32, device=dev)
+    e = torch.empty(B, dtype=torch.float64, device=dev)
+    ws_o = torch.empty(max(V.log_derivs_workspace(base, B), 1), dtype=torch.uint8, device=dev)
+    opts = sr_opts(V, "cg")
+    ws_sr = torch.empty(max(V.sr_workspace(B, P, opts), 1), dtype=torch.uint8, device=dev)
+    delta = torch.empty(P, dtype=torch.float64, device=dev)
+    for conv in convs:
+        gm = base.with_prec(conv)
+        lightcone = V.local_energy_workspace(gm, 1) > 0
+        nb = V.local_energy_workspace(gm, B)
+        ws_e = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
+        info = None
+        for it in range(2):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev[0].record()
+            V.vqmc_local_energy(gm, th, spins, out=e, workspace=ws_e)
+            ev[1].record()
+            V.vqmc_log_derivs(base, th, spins, O=O, workspace=ws_o)
+            ev[2].record()
+            _, _, info = V.vqmc_sr_solve(O, e, opts, delta=delta, workspace=ws_sr)
+            ev[3].record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        st = [ev[j].elapsed_time(ev[j + 1]) for j in range(3)]
+        fa, fe = eloc_flops(spins_np, L, C, n, lightcone, conv)
+        res[conv] = {"samples_per_s": B / wall, "ms_per_step": wall * 1e3,
+                     "stage_ms": {"local_energy": st[0], "log_derivs": st[1], "sr_solve": st[2]},
+                     "eloc": "lightcone" if lightcone else "dense",
+                     "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
+                     "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12,
+                     "cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
+                     "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9}
+        del ws_e
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +212,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual",
                     help="extra forms timed on the same inputs (comma list, or 'none')")
+    ap.add_argument("--also", default="24x24",
+                    help="another workload timed after the main one (one step per form, bf16x3 and fp32), "
+                         "or 'none'")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel that scales HBM byte counters, then exit")
     args = ap.parse_args()
@@ -308,6 +364,10 @@ def main():
                 del vws
     if variants:
         out["variants"] = variants
+    if args.also != "none" and args.also != args.workload:
+        del O, ws_o, ws_sr, ws_e
+        torch.cuda.empty_cache()
+        out["also"] = other_workload(V, torch, args.also, ["bf16x3", "fp32"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, th_np, spins_np, min(args.cpu_sample, B))
     print(json.dumps(out), flush=True)
