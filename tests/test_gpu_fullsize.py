@@ -1,0 +1,105 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times (the whole batch in one call): sampled outputs against the oracle
+(stored values at 24x24, live oracle calls at 10x10), and the SR solution
+against a property that holds at any size (the residual of
+(S + eps I) delta = F recomputed with plain FP64 torch algebra)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import R, V, models, to_dev, host, announce
+from vqmc_inputs import init_theta, uniform_sz0
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_large.json")
+
+
+def _golden(L):
+    return {c["L"]: c for c in json.load(open(GOLD))["cases"]}[L]
+
+
+def _residual(O, e, delta, eps):
+    """||(S + eps I) delta - F|| / ||F|| in FP64 from O (plain torch)."""
+    B = O.shape[0]
+    Oc = O.double()
+    Oc -= Oc.mean(dim=0)
+    ec = e - e.mean()
+    F = Oc.T @ ec / B
+    r = Oc.T @ (Oc @ delta) / B + eps * delta - F
+    return (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(F)).item()
+
+
+@pytest.mark.parametrize("prec", [V.PREC_BF16X3, V.PREC_FP32])
+def test_24x24_full_batch_sampled_against_oracle(prec):
+    """B = 16384 configurations in one light-cone call (the default form at
+    24x24); the first two are the configurations the stored oracle values
+    were computed on."""
+    g = _golden(24)
+    C, n = g["C"], g["n"]
+    B = 16384
+    gm, _ = models(24, C, n, prec)
+    th = to_dev(init_theta(C, n, seed=0))
+    s = to_dev(uniform_sz0(24, B, seed=1))
+    announce("24x24 full batch", prec)
+    flags = torch.full((B,), -1, dtype=torch.int32, device="cuda")
+    el = host(V.vqmc_local_energy(gm, th, s, flags=flags))
+    assert (host(flags) == 0).all() and np.isfinite(el).all()
+    ref = np.array(g["e_loc"])
+    rel = np.abs(el[:2] - ref) / np.abs(ref)
+    print("24x24 B=%d prec=%d E rel %s" % (B, prec, rel))
+    assert rel.max() <= (1e-4 if prec == V.PREC_FP32 else 1e-3)
+    assert abs(el[:2].mean() - ref.mean()) / abs(ref.mean()) <= (5e-5 if prec == V.PREC_FP32 else 1e-4)
+
+
+def test_24x24_full_batch_log_derivs_and_cg():
+    g = _golden(24)
+    C, n = g["C"], g["n"]
+    B = 16384
+    gm, _ = models(24, C, n)
+    th = to_dev(init_theta(C, n, seed=0))
+    s = to_dev(uniform_sz0(24, B, seed=1))
+    announce("24x24 full batch O and CG")
+    O = V.vqmc_log_derivs(gm, th, s)
+    O2 = host(O[:2])
+    idx = np.array(g["o_index"])
+    ref = np.array(g["o_values"])
+    got = np.take_along_axis(O2, idx.reshape(1, -1).repeat(2, 0), axis=1)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("24x24 O sampled max rel %.3e" % err)
+    assert err <= 1e-5
+    np.testing.assert_allclose(np.linalg.norm(O2, axis=1), g["o_row_norm"], rtol=1e-5)
+    e = V.vqmc_local_energy(gm.with_prec("bf16x3"), th, s)
+    d, F, info = V.vqmc_sr_solve(O, e, V.SrOpts(method=V.SR_CG, eps=1e-4, tol=1e-8, max_iter=200))
+    rr = _residual(O, e, d, 1e-4)
+    print("24x24 CG iters %d reported %.3e recomputed residual %.3e" % (info["iters"], info["rel_residual"], rr))
+    # the reported residual is the recursion's; the recomputed one agrees to
+    # the rounding of up to 200 FP64 iterations, and CG has reduced it
+    assert abs(rr - info["rel_residual"]) <= 1e-6 + 1e-3 * info["rel_residual"]
+    assert rr < 0.5
+
+
+def test_10x10_full_batch_sampled_against_oracle():
+    """B = 4096 configurations in one dense call (the bench's launch); 12
+    seeded samples recomputed by the oracle one by one."""
+    L, C, n, B = 10, 16, 6, 4096
+    th_np = init_theta(C, n, seed=0)
+    s_np = uniform_sz0(L, B, seed=5)
+    pick = np.random.default_rng(7).choice(B, 12, replace=False)
+    for prec in (V.PREC_FP32, V.PREC_BF16X3):
+        gm, rm = models(L, C, n, prec)
+        announce("10x10 full batch", prec)
+        el = host(V.vqmc_local_energy(gm, to_dev(th_np), to_dev(s_np)))
+        ref = R.local_energy(rm, th_np, s_np[pick])
+        rel = np.abs(el[pick] - ref) / np.maximum(np.abs(ref), 1.0)
+        print("10x10 B=%d prec=%d sampled per-sample rel max %.3e" % (B, prec, rel.max()))
+        assert rel.max() <= (1e-4 if prec == V.PREC_FP32 else 1e-3)
+    gm, rm = models(L, C, n)
+    O = host(V.vqmc_log_derivs(gm, to_dev(th_np), to_dev(s_np)))
+    Oref = R.log_derivs(rm, th_np, s_np[pick])
+    err = np.linalg.norm(O[pick] - Oref) / np.linalg.norm(Oref)
+    print("10x10 O sampled Frobenius rel %.3e" % err)
+    assert err <= 1e-5
