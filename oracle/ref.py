@@ -30,7 +30,8 @@ __all__ = [
 
 class _Model(ct.Structure):
     _fields_ = [("L", ct.c_int32), ("C", ct.c_int32), ("n", ct.c_int32),
-                ("J1", ct.c_double), ("J2", ct.c_double), ("marshall", ct.c_int32)]
+                ("J1", ct.c_double), ("J2", ct.c_double), ("marshall", ct.c_int32),
+                ("symmetry", ct.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -41,9 +42,10 @@ class RefModel:
     J1: float = 1.0
     J2: float = 0.5
     marshall: int = 1
+    symmetry: int = 0
 
     def c(self) -> _Model:
-        return _Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall)
+        return _Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, self.symmetry)
 
     @property
     def N(self) -> int:

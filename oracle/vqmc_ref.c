@@ -90,6 +90,55 @@ static int marshall_sign(const vqmc_ref_model *m, const int8_t *s) {
   return (up_a & 1) ? -1 : 1;
 }
 
+/* T^i S for the 90-degree rotation T of the L x L configuration (Eq.
+ * sym-ws): the element at (y, x) of T S is the element of S at (x, L-1-y),
+ * i.e. the whole square turned a quarter counter-clockwise. */
+static void rotate_config(int L, const int8_t *s, int i, int8_t *out) {
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      int sy = y, sx = x;
+      for (int k = 0; k < i; ++k) {
+        const int ty = sx, tx = L - 1 - sy;
+        sy = ty;
+        sx = tx;
+      }
+      out[y * L + x] = s[sy * L + sx];
+    }
+}
+
+/* log|W| and sign(W) of Sec. 2.2, W = (-1)^{N_up(A)} W_CNN with
+ * W_CNN = exp(sum of the last layer); with m->symmetry the sum of Eq.
+ * (sym-ws), W~ = sum_i W(T^i S), formed literally as a signed sum (scaled by
+ * the largest term).  lw (optional, [4]) receives the weights
+ * W(T^i S) / W~ of the four terms, which give d log|W~| = sum_i lw_i
+ * d log|W_CNN(T^i S)|. */
+static double amplitude(const vqmc_ref_model *m, const double *theta, const int8_t *s, int *sign,
+                        double *lw) {
+  if (!m->symmetry) {
+    if (sign) *sign = marshall_sign(m, s);
+    if (lw) lw[0] = 1.0;
+    return forward(m, theta, s, NULL);
+  }
+  const int L = m->L, N = L * L;
+  int8_t *r = (int8_t *)malloc((size_t)N);
+  double lg[4];
+  int sg[4];
+  double mx = -INFINITY;
+  for (int i = 0; i < 4; ++i) {
+    rotate_config(L, s, i, r);
+    lg[i] = forward(m, theta, r, NULL);
+    sg[i] = marshall_sign(m, r);
+    if (lg[i] > mx) mx = lg[i];
+  }
+  free(r);
+  double a = 0.0;
+  for (int i = 0; i < 4; ++i) a += sg[i] * exp(lg[i] - mx);
+  if (sign) *sign = a < 0.0 ? -1 : 1;
+  if (lw)
+    for (int i = 0; i < 4; ++i) lw[i] = sg[i] * exp(lg[i] - mx) / a;
+  return mx + log(fabs(a));
+}
+
 int vqmc_ref_log_psi(const vqmc_ref_model *m, const double *theta,
                      const int8_t *spins, int32_t B, double *log_abs,
                      int8_t *sign) {
@@ -97,8 +146,9 @@ int vqmc_ref_log_psi(const vqmc_ref_model *m, const double *theta,
   const int N = m->L * m->L;
 #pragma omp parallel for schedule(dynamic)
   for (int b = 0; b < B; ++b) {
-    log_abs[b] = forward(m, theta, spins + (size_t)b * N, NULL);
-    if (sign) sign[b] = (int8_t)marshall_sign(m, spins + (size_t)b * N);
+    int sg;
+    log_abs[b] = amplitude(m, theta, spins + (size_t)b * N, &sg, NULL);
+    if (sign) sign[b] = (int8_t)sg;
   }
   return 0;
 }
@@ -133,8 +183,10 @@ int vqmc_ref_local_energy(const vqmc_ref_model *m, const double *theta,
   /* all (sample, bond) pairs, so that OpenMP spreads the sigma' forwards */
   double *lp = (double *)malloc(sizeof(double) * ((size_t)B + 1));
   double *lpp = (double *)malloc(sizeof(double) * ((size_t)B * NB + 1));
+  int *sg0 = (int *)malloc(sizeof(int) * ((size_t)B + 1));
+  int *sgp = (int *)malloc(sizeof(int) * ((size_t)B * NB + 1));
 #pragma omp parallel for schedule(dynamic)
-  for (int b = 0; b < B; ++b) lp[b] = forward(m, theta, spins + (size_t)b * N, NULL);
+  for (int b = 0; b < B; ++b) lp[b] = amplitude(m, theta, spins + (size_t)b * N, &sg0[b], NULL);
 #pragma omp parallel for schedule(dynamic)
   for (int64_t t = 0; t < (int64_t)B * NB; ++t) {
     const int b = (int)(t / NB), k = (int)(t % NB);
@@ -143,18 +195,19 @@ int vqmc_ref_local_energy(const vqmc_ref_model *m, const double *theta,
     double J;
     bond(m, k, &i, &j, &J);
     lpp[t] = 0.0;
+    sgp[t] = 1;
     if (s[i] != s[j]) {
       int8_t *sp = (int8_t *)malloc((size_t)N);
       memcpy(sp, s, (size_t)N);
       sp[i] = s[j];
       sp[j] = s[i];
-      lpp[t] = forward(m, theta, sp, NULL);
+      lpp[t] = amplitude(m, theta, sp, &sgp[t], NULL);
       free(sp);
     }
   }
   for (int b = 0; b < B; ++b) {
     const int8_t *s = spins + (size_t)b * N;
-    const int sg = marshall_sign(m, s);
+    const int sg = sg0[b];
     double e = 0.0;
     int f = 0, sz = 0;
     for (int i = 0; i < N; ++i) {
@@ -168,12 +221,7 @@ int vqmc_ref_local_energy(const vqmc_ref_model *m, const double *theta,
       bond(m, k, &i, &j, &J);
       e += 0.25 * J * (double)s[i] * (double)s[j];
       if (s[i] != s[j]) {
-        int8_t *sp = (int8_t *)malloc((size_t)N);
-        memcpy(sp, s, (size_t)N);
-        sp[i] = s[j];
-        sp[j] = s[i];
-        const double mu = (double)(marshall_sign(m, sp) * sg);
-        free(sp);
+        const double mu = (double)(sgp[(size_t)b * NB + k] * sg);
         e += 0.5 * J * mu * exp(lpp[(size_t)b * NB + k] - lp[b]);
       }
     }
@@ -183,6 +231,8 @@ int vqmc_ref_local_energy(const vqmc_ref_model *m, const double *theta,
   }
   free(lp);
   free(lpp);
+  free(sg0);
+  free(sgp);
   return 0;
 }
 
@@ -246,6 +296,8 @@ static void log_derivs_one(const vqmc_ref_model *m, const double *theta,
   free(acts); free(h0); free(g); free(gp); free(dl);
 }
 
+/* With the symmetrised amplitude (Eq. sym-ws), d log|W~| = sum_i lw_i
+ * d log|W_CNN(T^i S)| with the term weights lw_i = W(T^i S) / W~. */
 int vqmc_ref_log_derivs(const vqmc_ref_model *m, const double *theta,
                         const int8_t *spins, int32_t B, double *O,
                         int64_t ldO) {
@@ -253,7 +305,26 @@ int vqmc_ref_log_derivs(const vqmc_ref_model *m, const double *theta,
   if (P < 0 || B < 0 || ldO < P || (B > 0 && (!theta || !spins || !O))) return -1;
   const int N = m->L * m->L;
 #pragma omp parallel for schedule(dynamic)
-  for (int b = 0; b < B; ++b) log_derivs_one(m, theta, spins + (size_t)b * N, O + (size_t)b * ldO);
+  for (int b = 0; b < B; ++b) {
+    const int8_t *s = spins + (size_t)b * N;
+    double *Ob = O + (size_t)b * ldO;
+    if (!m->symmetry) {
+      log_derivs_one(m, theta, s, Ob);
+      continue;
+    }
+    double lw[4];
+    amplitude(m, theta, s, NULL, lw);
+    int8_t *r = (int8_t *)malloc((size_t)N);
+    double *Oi = (double *)malloc(sizeof(double) * (size_t)P);
+    for (int64_t k = 0; k < P; ++k) Ob[k] = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      rotate_config(m->L, s, i, r);
+      log_derivs_one(m, theta, r, Oi);
+      for (int64_t k = 0; k < P; ++k) Ob[k] += lw[i] * Oi[k];
+    }
+    free(r);
+    free(Oi);
+  }
   return 0;
 }
 
@@ -453,7 +524,7 @@ int vqmc_ref_sample(const vqmc_ref_model *m, const double *theta,
   for (int b = 0; b < B; ++b) {
     int8_t *s = spins + (size_t)b * N;
     int8_t *sp = (int8_t *)malloc((size_t)N);
-    double lp = forward(m, theta, s, NULL);
+    double lp = amplitude(m, theta, s, NULL, NULL);
     int acc = 0;
     double mm = INFINITY;
     for (int64_t t = 0; t < (int64_t)n_sweeps * N; ++t) {
@@ -480,7 +551,7 @@ int vqmc_ref_sample(const vqmc_ref_model *m, const double *theta,
       sp[j] = s[i];
       if (proposal == 1) hastings = log((double)count_antiparallel_j1(m, s)) -
                                     log((double)count_antiparallel_j1(m, sp));
-      const double lpn = forward(m, theta, sp, NULL);
+      const double lpn = amplitude(m, theta, sp, NULL, NULL);
       const double r = ((double)w[1] + 0.5) * (1.0 / 4294967296.0);
       const double a = 2.0 * (lpn - lp) + hastings - log(r);
       if (fabs(a) < mm) mm = fabs(a);

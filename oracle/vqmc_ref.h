@@ -33,11 +33,16 @@ typedef struct {
   int32_t n;        /* C->C conv layers after the 1->C lift */
   double J1, J2;    /* couplings of Eq. (J1-J2) */
   int32_t marshall; /* 1: sign (-1)^{N_up(A)} (Sec. 2.2), 0: all signs +1 */
+  int32_t symmetry; /* 1: the rotation-symmetrised amplitude of Eq. (sym-ws),
+                       W~(S) = sum_{i=0..3} W(T^i S), T the 90-degree rotation
+                       of the L x L configuration; 0: W itself */
 } vqmc_ref_model;
 
 int64_t vqmc_ref_num_params(const vqmc_ref_model *m);
 
-/* log|W_CNN(sigma)| and the Marshall sign for B configurations [B][N]. */
+/* log|W| and the sign of W for B configurations [B][N]: W = (-1)^{N_up(A)}
+ * W_CNN (Sec. 2.2), or its rotation-symmetrised sum (Eq. sym-ws) when
+ * m->symmetry; log_abs is then log|sum_i W(T^i sigma)|. */
 int vqmc_ref_log_psi(const vqmc_ref_model *m, const double *theta,
                      const int8_t *spins, int32_t B, double *log_abs,
                      int8_t *sign);
@@ -48,7 +53,8 @@ int vqmc_ref_local_energy(const vqmc_ref_model *m, const double *theta,
                           const int8_t *spins, int32_t B, double *e_loc,
                           int32_t *flags);
 
-/* O[b][k] = d log|W(sigma_b)| / d theta_k, row stride ldO >= P. */
+/* O[b][k] = d log|W(sigma_b)| / d theta_k (W symmetrised when
+ * m->symmetry), row stride ldO >= P. */
 int vqmc_ref_log_derivs(const vqmc_ref_model *m, const double *theta,
                         const int8_t *spins, int32_t B, double *O,
                         int64_t ldO);

@@ -409,3 +409,114 @@ def test_sampler_reproducible_and_counter_split(theta4):
     c2 = R.sample(M4, theta4, c1[0], n_sweeps=2, seed=7, counter_base=16)
     assert (c2[0] == a[0]).all()
     assert ((c1[2] + c2[2]) == a[2]).all()
+
+
+# ------------------------------------- rotation-symmetrised amplitude
+
+M4S = R.RefModel(4, 4, 2, 1.0, 0.5, 1, 1)
+
+
+def _rot(states, L, k):
+    """numpy's quarter turn of each L x L configuration (k times)."""
+    return np.rot90(states.reshape(-1, L, L), k, axes=(1, 2)).reshape(len(states), L * L)
+
+
+def test_symmetrised_amplitude_definition_and_invariance():
+    """Eq. (sym-ws): log|sum_i W(T^i S)| equals the same sum formed here from
+    the oracle's own unsymmetrised amplitudes of numpy-rotated
+    configurations; it is invariant under the rotation, and for even L the
+    four Marshall signs agree (so the sum never cancels)."""
+    for L, C, n in ((4, 4, 2), (6, 4, 2), (8, 8, 1)):
+        m0 = R.RefModel(L, C, n)
+        ms = R.RefModel(L, C, n, 1.0, 0.5, 1, 1)
+        th = init_theta(C, n, seed=21).astype(np.float64)
+        s = uniform_sz0(L, 5, seed=22)
+        la, sg = R.log_psi(ms, th, s)
+        parts = [R.log_psi(m0, th, _rot(s, L, k)) for k in range(4)]
+        sgs = np.stack([p[1] for p in parts])
+        assert (sgs == sgs[0]).all() and (sg == sgs[0]).all()
+        lg = np.stack([p[0] for p in parts])
+        mx = lg.max(axis=0)
+        np.testing.assert_allclose(la, mx + np.log(np.exp(lg - mx).sum(axis=0)), rtol=1e-13)
+        for k in (1, 2, 3):
+            np.testing.assert_allclose(R.log_psi(ms, th, _rot(s, L, k))[0], la, rtol=1e-13)
+
+
+def _rotation_invariant_theta(C, n, seed):
+    """Every 3x3 kernel averaged over its four quarter turns: then
+    W_CNN(T S) = W_CNN(S) for every S."""
+    th = init_theta(C, n, seed=seed).astype(np.float64)
+    off = 0
+    for l in range(n + 1):
+        cin = 1 if l == 0 else C
+        W = th[off:off + C * cin * 9].reshape(C, cin, 3, 3)
+        W[:] = sum(np.rot90(W, k, axes=(2, 3)) for k in range(4)) / 4
+        off += C * cin * 9 + C
+    return th
+
+
+def test_symmetrised_closed_form_for_invariant_network():
+    """With rotation-invariant kernels the four terms are equal: log|W~| =
+    log W_CNN + log 4 and the local energy is that of the unsymmetrised
+    amplitude.  The log-derivatives are not: turning the input is turning
+    every kernel, so d/dW of the rotated term is the turned gradient, and
+    the symmetrised O is the unsymmetrised one averaged over the four quarter
+    turns of each 3x3 kernel gradient (biases unchanged)."""
+    L, C, n = 6, 4, 2
+    m0, ms = R.RefModel(L, C, n), R.RefModel(L, C, n, 1.0, 0.5, 1, 1)
+    th = _rotation_invariant_theta(C, n, 23)
+    s = uniform_sz0(L, 4, seed=24)
+    np.testing.assert_allclose(R.log_psi(ms, th, s)[0], R.log_psi(m0, th, s)[0] + math.log(4), rtol=1e-13)
+    np.testing.assert_allclose(R.local_energy(ms, th, s), R.local_energy(m0, th, s), rtol=1e-12)
+    O0 = R.log_derivs(m0, th, s)
+    Oavg = O0.copy()
+    off = 0
+    for l in range(n + 1):
+        cin = 1 if l == 0 else C
+        G = O0[:, off:off + C * cin * 9].reshape(-1, C, cin, 3, 3)
+        Oavg[:, off:off + C * cin * 9] = (sum(np.rot90(G, k, axes=(3, 4)) for k in range(4)) / 4).reshape(-1, C * cin * 9)
+        off += C * cin * 9 + C
+    np.testing.assert_allclose(R.log_derivs(ms, th, s), Oavg, rtol=1e-10, atol=1e-12)
+
+
+def test_symmetrised_enumeration_identity(ham4, theta4):
+    """sum_s |psi~|^2 E_loc(s) = <psi~|H|psi~> and E_loc = (H psi~)/psi~ over
+    all 12870 states of 4x4 with the symmetrised amplitude."""
+    H, states = ham4
+    la, sg = R.log_psi(M4S, theta4, states)
+    el = R.local_energy(M4S, theta4, states)
+    w = np.exp(2 * (la - la.max()))
+    assert (w * el).sum() / w.sum() == pytest.approx(R.exact_energy(H, la, sg), rel=1e-12)
+    psi = sg * np.exp(la - la.max())
+    np.testing.assert_allclose(el, (H @ psi) / psi, rtol=1e-11, atol=1e-11)
+
+
+def test_symmetrised_log_derivs_central_fd():
+    ms = R.RefModel(4, 4, 2, 1.0, 0.5, 1, 1)
+    th = init_theta(4, 2, seed=25).astype(np.float64)
+    s = uniform_sz0(4, 5, seed=26)
+    O = R.log_derivs(ms, th, s)
+    rng = np.random.default_rng(27)
+    h = 1e-6
+    for k in rng.choice(th.size, 30, replace=False):
+        tp, tm = th.copy(), th.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (R.log_psi(ms, tp, s)[0] - R.log_psi(ms, tm, s)[0]) / (2 * h)
+        np.testing.assert_allclose(O[:, k], fd, rtol=1e-6, atol=1e-8)
+
+
+def test_symmetrised_sampler_distribution_4x4(ham4, theta4):
+    H, states = ham4
+    la, sg = R.log_psi(M4S, theta4, states)
+    chains = 1024
+    s, lab, _, _ = R.sample(M4S, theta4, neel(4, chains), n_sweeps=50, seed=4321)
+    np.testing.assert_allclose(lab, R.log_psi(M4S, theta4, s)[0], rtol=1e-12)
+    p = np.exp(2 * (la - la.max()))
+    p /= p.sum()
+    ms = _stag(states, 4)
+    hist = np.bincount(_stag(s, 4), minlength=9)[:9]
+    exp = np.array([p[ms == k].sum() for k in range(9)]) * chains
+    keep = exp > 5
+    chi2 = (((hist[keep] - exp[keep]) ** 2) / exp[keep]).sum()
+    assert chi2 < 3 * keep.sum() + 20, (hist, exp)
