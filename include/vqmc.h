@@ -83,13 +83,22 @@ typedef enum { VQMC_ELOC_AUTO = 0, VQMC_ELOC_DENSE = 1, VQMC_ELOC_LIGHTCONE = 2 
  *   conv_prec  vqmc_prec of the forward convolutions (log psi, local energy
  *              and sampler; with LIGHTCONE, of the convolutions of the
  *              activation changes).  The log-derivative path always runs FP32;
- *   eloc_mode  vqmc_eloc_mode. */
+ *   eloc_mode  vqmc_eloc_mode;
+ *   symmetry   0: the amplitude W above; 1: the rotation-symmetrised
+ *              W~(S) = sum_{i=0..3} W(T^i S) of Eq. (sym-ws), T the quarter
+ *              turn of the lattice, (T S) at (y, x) = S at (x, L-1-y).  On an
+ *              even lattice T maps sublattice A onto B, and for Sz = 0 N/2 is
+ *              even, so the four Marshall signs agree: every entry point
+ *              evaluates log|W~| = logsumexp_i log W_CNN(T^i S) with the sign
+ *              of S (for Sz != 0, which the local energy flags, the unsigned
+ *              sum).  Costs four forward passes per configuration. */
 typedef struct {
   int32_t L, channels, n_layers, activation;
   double J1, J2;
   int32_t marshall;
   int32_t conv_prec;
   int32_t eloc_mode;
+  int32_t symmetry;
 } vqmc_model;
 
 /* Number of parameters P = (9C + C) + n (9C^2 + C); < 0 for an invalid model. */
@@ -110,7 +119,8 @@ const char *vqmc_status_string(vqmc_status s);
  *               order, with the Hastings factor n_ap(s) / n_ap(s');
  * and accepts iff 2 (log|W'| - log|W|) [+ ln Hastings] >= ln r with
  * r = (u1 + 1/2) 2^-32 (the paper's P = (W'/W)^2 >= r, r in (0,1)).
- * log_psi (dev double [B], nullable) receives the final log|W_CNN|;
+ * log_psi (dev double [B], nullable) receives the final log|W_CNN| (with
+ * symmetry, log|W~|: every proposal then evaluates the four rotations);
  * n_accepted (dev int32 [B], nullable) the accepted moves.  B >= 0. */
 vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8_t *spins,
                         double *log_psi, int32_t B, int32_t n_sweeps,
@@ -118,7 +128,8 @@ vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8_t *spins,
                         int32_t *n_accepted, hipStream_t stream);
 
 /* log|W_CNN(sigma_b)| (dev double [B]) and the Marshall sign (dev int8 [B],
- * nullable; +1 when marshall = 0) of B configurations (Sec. 2.2). */
+ * nullable; +1 when marshall = 0) of B configurations (Sec. 2.2); with
+ * symmetry, log|W~(sigma_b)|, the logsumexp over the four rotations. */
 vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta,
                          const int8_t *spins, int32_t B, double *log_abs_psi,
                          int8_t *sign, hipStream_t stream);
@@ -132,6 +143,12 @@ vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta,
  * on chip and evaluated in the same launch.  e_loc: dev double [B].
  * chain_flags (dev int32 [B], nullable): bit 1 non-finite log psi or E_s,
  * bit 2 Sz != 0, bit 4 a spin value other than +-1; the status stays OK.
+ * With symmetry, W~(s')/W~(s) = sum_i p_i mu W_CNN(T^i s')/W_CNN(T^i s) with
+ * p_i = W_CNN(T^i s)/sum_j W_CNN(T^j s), and the exchanges of T^i s are the
+ * rotated exchanges of s (the bond set maps onto itself, J1 to J1 and J2 to
+ * J2), so E_s = sum_i p_i E_CNN(T^i s): the 4B rotated configurations are
+ * written to the workspace, evaluated by either method above, and combined;
+ * bit 1 of chain_flags is set if any rotation's value is non-finite.
  * workspace: dev, at least vqmc_local_energy_workspace bytes (may be NULL
  * when that is 0). */
 vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
@@ -140,7 +157,7 @@ vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                               size_t ws_bytes, hipStream_t stream);
 
 /* Workspace (device bytes) vqmc_local_energy needs for this model and B
- * (0 for the dense evaluation). */
+ * (0 for the dense evaluation without symmetry). */
 vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes);
 
 /* Workspace (device bytes) needed by vqmc_log_derivs for this model. */
@@ -148,7 +165,11 @@ vqmc_status vqmc_log_derivs_workspace(const vqmc_model *m, int32_t B, size_t *by
 
 /* Per-sample log-derivatives O[b][k] = d log|W(sigma_b)| / d theta_k (the
  * O_s of Eq. Es-Os-G), FP32, by a hand-written reverse pass that recomputes
- * the forward activations per sample.  O: dev float [B][ldO], ldO >= P.
+ * the forward activations per sample.  With symmetry, d log|W~| =
+ * sum_i p_i d log W_CNN(T^i S) (p_i as for the local energy): the reverse
+ * pass runs once per rotation and the rows are accumulated in place with
+ * running rescaling (the largest weight kept at 1 until the final
+ * normalisation).  O: dev float [B][ldO], ldO >= P.
  * workspace: dev, at least the bytes vqmc_log_derivs_workspace reports. */
 vqmc_status vqmc_log_derivs(const vqmc_model *m, const float *theta,
                             const int8_t *spins, int32_t B, float *O, int64_t ldO,

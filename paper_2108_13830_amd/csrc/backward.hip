@@ -12,6 +12,14 @@
 //   g_l[j][ci]        = sum_{tap,co} D[j - d(tap)][co] W_l[co][ci][tap]   (transposed conv)
 //   D <- g_l * (1 - H^2)
 // and finishes with the 1 -> C lift, whose input is the spin configuration.
+//
+// Symmetrised amplitude (R = 4 rotations): d log|W~| = sum_r p_r O(T^r S)
+// with p_r the softmax of log W_CNN(T^r S).  The passes run rotation by
+// rotation and accumulate into the sample's row of O in place: after
+// rotation r the row holds sum_{i<=r} exp(lw_i - M_r) O_i (M_r the running
+// maximum), so each pass scales the row by exp(M_{r-1} - M_r) and its own
+// delta_{n+1} by exp(lw_r - M_r); the last pass also divides both by the
+// normaliser.  With R = 1 the row is simply written.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,7 +63,7 @@ template <int C, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void logderiv_kernel(const float *__restrict__ theta,
                                                            const float *__restrict__ frags,
                                                            const int8_t *__restrict__ spins, int B,
-                                                           int L, int n_layers, float *__restrict__ O,
+                                                           int L, int n_layers, int R, float *__restrict__ O,
                                                            int64_t ldO, float *__restrict__ scratch_all) {
   using K = Bwd<C, NW, TPW>;
   using E = typename K::E;
@@ -63,143 +71,169 @@ __global__ __launch_bounds__(NW * 64) void logderiv_kernel(const float *__restri
   __shared__ __align__(16) float s_D[E::MAXROWS * LDA];
   __shared__ __align__(16) float s_H[E::MAXROWS * LDA];
   __shared__ int8_t s_sp[E::MAXROWS];
+  __shared__ double s_red[NW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = L * L;
   float *scratch = scratch_all + (size_t)blockIdx.x * n_layers * N * C;
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     float *Ob = O + (size_t)b * ldO;
-    for (int i = tid; i < N; i += E::NTHR) s_sp[i] = spins[(size_t)b * N + i];
-    __syncthreads();
-    // ---- forward, keeping h_1..h_n
-    E::lift(theta, s_sp, N, L, N, reinterpret_cast<char *>(s_D));
-    __syncthreads();
-    for (int idx = tid; idx < N * C; idx += E::NTHR) {
-      const int r = idx / C, c = idx - r * C;
-      scratch[idx] = s_D[r * LDA + c];
-    }
-    for (int l = 1; l <= n_layers; ++l) {
-      f32x4 acc[TPW][E::NT];
-      E::template kloop<true, 1>(reinterpret_cast<const char *>(s_D),
-                                 reinterpret_cast<const char *>(frags + (size_t)(l - 1) * 2 * K::PER),
-                                 N, L, N, acc);
+    double mx = -INFINITY, zsum = 0.0;  // running maximum and normaliser (uniform)
+    for (int rr = 0; rr < R; ++rr) {
+      for (int i = tid; i < N; i += E::NTHR) s_sp[i] = spins[(size_t)b * N + rot_src(i, rr, L)];
       __syncthreads();
-      E::write_tiles(acc, theta + layer_offset(C, l) + 9 * C * C, N, reinterpret_cast<char *>(s_D),
-                     l < n_layers ? scratch + (size_t)l * N * C : nullptr);
+      // ---- forward, keeping h_1..h_n
+      E::lift(theta, s_sp, N, L, N, reinterpret_cast<char *>(s_D));
       __syncthreads();
-    }
-    // ---- delta_{n+1} = 1 - h_{n+1}^2 (the head sums h_{n+1})
-    for (int idx = tid; idx < N * C; idx += E::NTHR) {
-      const int r = idx / C, c = idx - r * C;
-      const float h = s_D[r * LDA + c];
-      s_D[r * LDA + c] = 1.f - h * h;
-    }
-    // ---- reverse pass over the C -> C layers
-    for (int l = n_layers; l >= 1; --l) {
-      const float *hl = scratch + (size_t)(l - 1) * N * C;
       for (int idx = tid; idx < N * C; idx += E::NTHR) {
         const int r = idx / C, c = idx - r * C;
-        s_H[r * LDA + c] = hl[idx];
+        scratch[idx] = s_D[r * LDA + c];
       }
-      __syncthreads();
-      const int64_t off = layer_offset(C, l);
-      // dW_l and db_l: M = c_out, columns n' = ci*9 + tap (n' = 9C: bias), K = sites
-      {
-        f32x4 acc[K::MT][K::NPW];
-        int cdy[K::NPW], cdx[K::NPW], cci[K::NPW];
-        bool cval[K::NPW], cone[K::NPW];
-#pragma unroll
-        for (int q = 0; q < K::NPW; ++q) {
-          const int np = (wave + q * NW) * 16 + (lane & 15);
-          const int ci = np / 9, tap = np - ci * 9;
-          cval[q] = np < 9 * C;
-          cone[q] = np == 9 * C;
-          cci[q] = cval[q] ? ci : 0;
-          cdy[q] = tap / 3 - 1;
-          cdx[q] = tap % 3 - 1;
-#pragma unroll
-          for (int mt = 0; mt < K::MT; ++mt) acc[mt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int l = 1; l <= n_layers; ++l) {
+        f32x4 acc[TPW][E::NT];
+        E::template kloop<true, 1>(reinterpret_cast<const char *>(s_D),
+                                   reinterpret_cast<const char *>(frags + (size_t)(l - 1) * 2 * K::PER),
+                                   N, L, N, acc);
+        __syncthreads();
+        E::write_tiles(acc, theta + layer_offset(C, l) + 9 * C * C, N, reinterpret_cast<char *>(s_D),
+                       l < n_layers ? scratch + (size_t)l * N * C : nullptr);
+        __syncthreads();
+      }
+      // ---- this rotation's weight: row <- alpha row + beta O(T^r S)
+      float alpha = 0.f, beta = 1.f;
+      if (R > 1) {
+        double part = 0.0;
+        for (int idx = tid; idx < N * C; idx += E::NTHR) {
+          const int row = idx / C, c = idx - row * C;
+          part += (double)s_D[row * LDA + c];
         }
-        int site = lane >> 4;
-        int y = site / L, x = site - y * L;
-        for (int ks = 0; ks < N / 4; ++ks) {
-          float a[K::MT];
-#pragma unroll
-          for (int mt = 0; mt < K::MT; ++mt) {
-            const int co = mt * 16 + (lane & 15);
-            a[mt] = co < C ? s_D[site * LDA + co] : 0.f;
-          }
-#pragma unroll
+        part = wave_sum(part);
+        if (lane == 0) s_red[wave] = part;
+        __syncthreads();
+        double lw = 0.0;
+  #pragma unroll
+        for (int w = 0; w < NW; ++w) lw += s_red[w];
+        __syncthreads();
+        const double m2 = fmax(mx, lw), sc = exp(mx - m2), wr = exp(lw - m2);
+        zsum = zsum * sc + wr;
+        mx = m2;
+        const double norm = rr == R - 1 ? 1.0 / zsum : 1.0;
+        alpha = (float)(sc * norm);
+        beta = (float)(wr * norm);
+      }
+      // ---- delta_{n+1} = beta (1 - h_{n+1}^2) (the head sums h_{n+1})
+      for (int idx = tid; idx < N * C; idx += E::NTHR) {
+        const int row = idx / C, c = idx - row * C;
+        const float h = s_D[row * LDA + c];
+        s_D[row * LDA + c] = beta * (1.f - h * h);
+      }
+      // ---- reverse pass over the C -> C layers
+      for (int l = n_layers; l >= 1; --l) {
+        const float *hl = scratch + (size_t)(l - 1) * N * C;
+        for (int idx = tid; idx < N * C; idx += E::NTHR) {
+          const int r = idx / C, c = idx - r * C;
+          s_H[r * LDA + c] = hl[idx];
+        }
+        __syncthreads();
+        const int64_t off = layer_offset(C, l);
+        // dW_l and db_l: M = c_out, columns n' = ci*9 + tap (n' = 9C: bias), K = sites
+        {
+          f32x4 acc[K::MT][K::NPW];
+          int cdy[K::NPW], cdx[K::NPW], cci[K::NPW];
+          bool cval[K::NPW], cone[K::NPW];
+  #pragma unroll
           for (int q = 0; q < K::NPW; ++q) {
-            if ((wave + q * NW) < K::NTN) {
-              const int nb = wrapL(y + cdy[q], L) * L + wrapL(x + cdx[q], L);
-              const float bv = cval[q] ? s_H[nb * LDA + cci[q]] : (cone[q] ? 1.f : 0.f);
-#pragma unroll
-              for (int mt = 0; mt < K::MT; ++mt) acc[mt][q] = mma_f32(a[mt], bv, acc[mt][q]);
+            const int np = (wave + q * NW) * 16 + (lane & 15);
+            const int ci = np / 9, tap = np - ci * 9;
+            cval[q] = np < 9 * C;
+            cone[q] = np == 9 * C;
+            cci[q] = cval[q] ? ci : 0;
+            cdy[q] = tap / 3 - 1;
+            cdx[q] = tap % 3 - 1;
+  #pragma unroll
+            for (int mt = 0; mt < K::MT; ++mt) acc[mt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
+          int site = lane >> 4;
+          int y = site / L, x = site - y * L;
+          for (int ks = 0; ks < N / 4; ++ks) {
+            float a[K::MT];
+  #pragma unroll
+            for (int mt = 0; mt < K::MT; ++mt) {
+              const int co = mt * 16 + (lane & 15);
+              a[mt] = co < C ? s_D[site * LDA + co] : 0.f;
             }
-          }
-          site += 4;
-          x += 4;
-          while (x >= L) {
-            x -= L;
-            ++y;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < K::NPW; ++q) {
-          const int np = (wave + q * NW) * 16 + (lane & 15);
-          if ((wave + q * NW) < K::NTN) {
-#pragma unroll
-            for (int mt = 0; mt < K::MT; ++mt)
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                const int co = mt * 16 + (lane >> 4) * 4 + j;
-                if (co < C) {
-                  if (np < 9 * C) Ob[off + (int64_t)co * 9 * C + np] = acc[mt][q][j];
-                  else if (np == 9 * C) Ob[off + 9 * C * C + co] = acc[mt][q][j];
-                }
+  #pragma unroll
+            for (int q = 0; q < K::NPW; ++q) {
+              if ((wave + q * NW) < K::NTN) {
+                const int nb = wrapL(y + cdy[q], L) * L + wrapL(x + cdx[q], L);
+                const float bv = cval[q] ? s_H[nb * LDA + cci[q]] : (cone[q] ? 1.f : 0.f);
+  #pragma unroll
+                for (int mt = 0; mt < K::MT; ++mt) acc[mt][q] = mma_f32(a[mt], bv, acc[mt][q]);
               }
+            }
+            site += 4;
+            x += 4;
+            while (x >= L) {
+              x -= L;
+              ++y;
+            }
           }
-        }
-      }
-      // g_l = transposed conv of delta_{l+1}; then delta_l = g_l (1 - h_l^2)
-      f32x4 acc[TPW][E::NT];
-      E::template kloop<true, -1>(reinterpret_cast<const char *>(s_D),
-                                  reinterpret_cast<const char *>(frags + (size_t)(l - 1) * 2 * K::PER + K::PER),
-                                  N, L, N, acc);
-      __syncthreads();
-#pragma unroll
-      for (int nt = 0; nt < E::NT; ++nt) {
-        const int ci = nt * 16 + (lane & 15);
-#pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + j;
-            if (row < N && ci < C) {
-              const float h = s_H[row * LDA + ci];
-              s_D[row * LDA + ci] = acc[i][nt][j] * (1.f - h * h);
+  #pragma unroll
+          for (int q = 0; q < K::NPW; ++q) {
+            const int np = (wave + q * NW) * 16 + (lane & 15);
+            if ((wave + q * NW) < K::NTN) {
+  #pragma unroll
+              for (int mt = 0; mt < K::MT; ++mt)
+  #pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const int co = mt * 16 + (lane >> 4) * 4 + j;
+                  if (co < C) {
+                    float *dst = np < 9 * C ? Ob + off + (int64_t)co * 9 * C + np : Ob + off + 9 * C * C + co;
+                    if (np <= 9 * C) *dst = rr ? fmaf(alpha, *dst, acc[mt][q][j]) : acc[mt][q][j];
+                  }
+                }
             }
           }
         }
+        // g_l = transposed conv of delta_{l+1}; then delta_l = g_l (1 - h_l^2)
+        f32x4 acc[TPW][E::NT];
+        E::template kloop<true, -1>(reinterpret_cast<const char *>(s_D),
+                                    reinterpret_cast<const char *>(frags + (size_t)(l - 1) * 2 * K::PER + K::PER),
+                                    N, L, N, acc);
+        __syncthreads();
+  #pragma unroll
+        for (int nt = 0; nt < E::NT; ++nt) {
+          const int ci = nt * 16 + (lane & 15);
+  #pragma unroll
+          for (int i = 0; i < TPW; ++i) {
+  #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + j;
+              if (row < N && ci < C) {
+                const float h = s_H[row * LDA + ci];
+                s_D[row * LDA + ci] = acc[i][nt][j] * (1.f - h * h);
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+      // ---- the 1 -> C lift: dW_0[co][tap] = sum_site D[site][co] s[site + d(tap)]
+      for (int o = tid; o < 10 * C; o += E::NTHR) {
+        const int co = o < 9 * C ? o / 9 : o - 9 * C;
+        const int tap = o < 9 * C ? o - co * 9 : -1;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        float sum = 0.f;
+        for (int y = 0; y < L; ++y) {
+          const int yy = wrapL(y + dy, L) * L;
+          for (int x = 0; x < L; ++x) {
+            const float d = s_D[(y * L + x) * LDA + co];
+            sum += tap < 0 ? d : d * (float)s_sp[yy + wrapL(x + dx, L)];
+          }
+        }
+        Ob[o] = rr ? fmaf(alpha, Ob[o], sum) : sum;
       }
       __syncthreads();
     }
-    // ---- the 1 -> C lift: dW_0[co][tap] = sum_site D[site][co] s[site + d(tap)]
-    for (int o = tid; o < 10 * C; o += E::NTHR) {
-      const int co = o < 9 * C ? o / 9 : o - 9 * C;
-      const int tap = o < 9 * C ? o - co * 9 : -1;
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      float sum = 0.f;
-      for (int y = 0; y < L; ++y) {
-        const int yy = wrapL(y + dy, L) * L;
-        for (int x = 0; x < L; ++x) {
-          const float d = s_D[(y * L + x) * LDA + co];
-          sum += tap < 0 ? d : d * (float)s_sp[yy + wrapL(x + dx, L)];
-        }
-      }
-      Ob[o] = sum;
-    }
-    __syncthreads();
   }
 }
 
@@ -259,8 +293,8 @@ static vqmc_status launch_bwd(const vqmc_model *m, const float *theta, const int
   const int total = (int)frag_floats(C, n);
   pack_frags_kernel<C><<<(total + 255) / 256, 256, 0, stream>>>(theta, n, frags);
   VQMC_LAUNCH_CHECK();
-  logderiv_kernel<C, 4, TPW><<<bwd_grid<C, TPW>(B), 256, 0, stream>>>(theta, frags, spins, B, m->L, n,
-                                                                      O, ldO, scratch);
+  logderiv_kernel<C, 4, TPW><<<bwd_grid<C, TPW>(B), 256, 0, stream>>>(
+      theta, frags, spins, B, m->L, n, m->symmetry ? 4 : 1, O, ldO, scratch);
   VQMC_LAUNCH_CHECK();
   (void)N;
   return VQMC_OK;

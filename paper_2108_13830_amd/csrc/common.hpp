@@ -22,6 +22,7 @@ inline bool model_valid(const vqmc_model *m) {
   if (m->conv_prec < VQMC_PREC_FP32 || m->conv_prec > VQMC_PREC_BF16X3) return false;
   if (m->conv_prec != VQMC_PREC_FP32 && m->channels % 8 != 0) return false;
   if (m->eloc_mode < VQMC_ELOC_AUTO || m->eloc_mode > VQMC_ELOC_LIGHTCONE) return false;
+  if (m->symmetry != 0 && m->symmetry != 1) return false;
   return true;
 }
 

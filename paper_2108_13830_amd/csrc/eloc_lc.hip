@@ -194,7 +194,8 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
                                                           int n_layers, double J1, double J2, int marshall,
                                                           float *__restrict__ zscratch,
                                                           double *__restrict__ e_loc,
-                                                          int32_t *__restrict__ flags) {
+                                                          int32_t *__restrict__ flags,
+                                                          double *__restrict__ lp_out) {
   using K = LC<C, PREC, NW, TPW>;
   using E32 = typename K::E32;
   using EP = typename K::EP;
@@ -290,6 +291,14 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         }
         wait_copies();
         __syncthreads();
+      }
+      if (lp_out) {
+        // log|W_CNN(s)| from the stored last-layer pre-activations
+        const float *zn = zsc + (size_t)n_layers * N * C;
+        double lp = 0.0;
+        for (int idx = tid; idx < N * C; idx += NW * 64) lp += (double)tanh_f(zn[idx]);
+        lp = bsum<NW>(lp, s_red);
+        if (tid == 0) lp_out[b] = lp;
       }
     }
 
@@ -501,7 +510,7 @@ size_t lc_ws(const vqmc_model *m, int B) {
 
 template <int C, int PREC, int NW, int TPW>
 vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
-                      int32_t *flags, char *ws, hipStream_t st) {
+                      int32_t *flags, double *lp, char *ws, hipStream_t st) {
   const int n = m->n_layers;
   char *f32 = ws;
   char *fp = ws + al256(n * frag_bytes_per_layer<C, P_F32>());
@@ -512,19 +521,19 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
   if (PREC != P_F32) pack_lc_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
   else fp = f32;
   eloc_lc_kernel<C, PREC, NW, TPW><<<lc_grid<C, PREC, NW, TPW>(B), NW * 64, 0, st>>>(
-      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags);
+      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags, lp);
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
   return VQMC_OK;
 }
 
 template <int C, int PREC>
 vqmc_status lc_launch_c(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
-                        int32_t *flags, char *ws, hipStream_t st) {
+                        int32_t *flags, double *lp, char *ws, hipStream_t st) {
   switch (lc_shape(m->L * m->L)) {
-    case 0: return lc_launch<C, PREC, 4, 1>(m, theta, spins, B, e_loc, flags, ws, st);
-    case 1: return lc_launch<C, PREC, 4, 2>(m, theta, spins, B, e_loc, flags, ws, st);
-    case 2: return lc_launch<C, PREC, 8, 2>(m, theta, spins, B, e_loc, flags, ws, st);
-    default: return lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, ws, st);
+    case 0: return lc_launch<C, PREC, 4, 1>(m, theta, spins, B, e_loc, flags, lp, ws, st);
+    case 1: return lc_launch<C, PREC, 4, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
+    case 2: return lc_launch<C, PREC, 8, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
+    default: return lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, lp, ws, st);
   }
 }
 
@@ -545,17 +554,17 @@ size_t eloc_lc_workspace(const vqmc_model *m, int B) {
 bool eloc_lc_supported(const vqmc_model *m) { return m->channels == 16 || m->channels == 32; }
 
 vqmc_status eloc_lc(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
-                    int32_t *flags, void *ws, hipStream_t st) {
+                    int32_t *flags, double *lp, void *ws, hipStream_t st) {
   char *w = reinterpret_cast<char *>(ws);
   switch (m->channels) {
     case 16:
-      return m->conv_prec == P_F32 ? lc_launch_c<16, P_F32>(m, theta, spins, B, e_loc, flags, w, st)
-             : m->conv_prec == P_BF16 ? lc_launch_c<16, P_BF16>(m, theta, spins, B, e_loc, flags, w, st)
-                                      : lc_launch_c<16, P_X3>(m, theta, spins, B, e_loc, flags, w, st);
+      return m->conv_prec == P_F32 ? lc_launch_c<16, P_F32>(m, theta, spins, B, e_loc, flags, lp, w, st)
+             : m->conv_prec == P_BF16 ? lc_launch_c<16, P_BF16>(m, theta, spins, B, e_loc, flags, lp, w, st)
+                                      : lc_launch_c<16, P_X3>(m, theta, spins, B, e_loc, flags, lp, w, st);
     case 32:
-      return m->conv_prec == P_F32 ? lc_launch_c<32, P_F32>(m, theta, spins, B, e_loc, flags, w, st)
-             : m->conv_prec == P_BF16 ? lc_launch_c<32, P_BF16>(m, theta, spins, B, e_loc, flags, w, st)
-                                      : lc_launch_c<32, P_X3>(m, theta, spins, B, e_loc, flags, w, st);
+      return m->conv_prec == P_F32 ? lc_launch_c<32, P_F32>(m, theta, spins, B, e_loc, flags, lp, w, st)
+             : m->conv_prec == P_BF16 ? lc_launch_c<32, P_BF16>(m, theta, spins, B, e_loc, flags, lp, w, st)
+                                      : lc_launch_c<32, P_X3>(m, theta, spins, B, e_loc, flags, lp, w, st);
     default: return VQMC_ERR_ARG;
   }
 }

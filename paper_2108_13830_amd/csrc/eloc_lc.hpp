@@ -15,8 +15,9 @@ bool eloc_lc_supported(const vqmc_model *m);
 // slice of FP32 pre-activations (all layers of one sample) per workgroup.
 size_t eloc_lc_workspace(const vqmc_model *m, int B);
 
-// Enqueue the light-cone local energy of B samples on st.
+// Enqueue the light-cone local energy of B samples on st; lp (dev double
+// [B], nullable) receives log|W_CNN(s)| of each sample's FP32 pass.
 vqmc_status eloc_lc(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
-                    int32_t *flags, void *ws, hipStream_t st);
+                    int32_t *flags, double *lp, void *ws, hipStream_t st);
 
 }  // namespace vqmc

@@ -36,6 +36,18 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_X3 = 2 };
 
 __device__ __forceinline__ int wrapL(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
 
+// Site of S read at site i of T^r S, T the quarter turn of Eq. (sym-ws):
+// (T S)(y, x) = S(x, L-1-y), so T^2 reads (L-1-y, L-1-x) and T^3 (L-1-x, y).
+__device__ __forceinline__ int rot_src(int i, int r, int L) {
+  const int y = i / L, x = i - y * L;
+  switch (r) {
+    case 0: return i;
+    case 1: return x * L + (L - 1 - y);
+    case 2: return (L - 1 - y) * L + (L - 1 - x);
+    default: return (L - 1 - x) * L + y;
+  }
+}
+
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   __bf16 h = (__bf16)x;
   return __builtin_bit_cast(uint16_t, h);

@@ -93,34 +93,85 @@ __device__ __forceinline__ void philox(uint32_t &c0, uint32_t &c1, uint32_t &c2,
 
 // ------------------------------------------------------------- log |psi|
 
-template <int C, int PREC, int NW, int TPW>
+// logsumexp of v[0..R) in FP64 (the largest term factored out).
+__device__ __forceinline__ double lse(const double *v, int R) {
+  double mx = v[0];
+  for (int r = 1; r < R; ++r) mx = fmax(mx, v[r]);
+  double t = 0.0;
+  for (int r = 0; r < R; ++r) t += exp(v[r] - mx);
+  return mx + log(t);
+}
+
+// SYM = false: one configuration per slot, G per workgroup.  SYM (R = 4
+// rotations, the symmetrised amplitude): every configuration fills R
+// consecutive slots with its rotations T^r S, read straight from global
+// memory through rot_src.  When R slots fit a batch (G >= R) a workgroup
+// takes G/R whole configurations per forward pass; otherwise it takes one
+// configuration and thread 0 folds the log|W| of its rotations, G per pass,
+// into a running logsumexp kept in LDS.
+template <int C, int PREC, int NW, int TPW, bool SYM>
 __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void logpsi_kernel(const float *__restrict__ theta,
                                                          const int8_t *__restrict__ spins, int B,
                                                          int L, int n_layers, int marshall, int G,
                                                          double *__restrict__ out,
                                                          int8_t *__restrict__ sign) {
   using E = Engine<C, PREC, NW, TPW>;
+  constexpr int R = SYM ? 4 : 1;
   __shared__ __align__(16) char s_act[E::ACT_BYTES];
   __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
   __shared__ int8_t s_sp[E::MAXROWS];
   __shared__ uint16_t s_nbt[E::NBT_ELEMS];
   __shared__ double s_lp[64];
+  __shared__ int s_ired[NW];
+  __shared__ double s_run[2];  // running maximum and sum of the logsumexp
   const int N = L * L;
-  E::build_nbt(s_nbt, G, L, N);
-  for (int base = blockIdx.x * G; base < B; base += gridDim.x * G) {
-    const int Gb = min(G, B - base);
-    for (int idx = threadIdx.x; idx < Gb * N; idx += E::NTHR) s_sp[idx] = spins[(size_t)base * N + idx];
-    __syncthreads();
-    E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
-    for (int g = threadIdx.x; g < Gb; g += E::NTHR) {
-      out[base + g] = s_lp[g];
-      if (sign) {
-        int up = 0;
-        for (int i = 0; i < N; ++i) {
-          const int y = i / L, x = i - y * L;
-          up += (((x + y) & 1) == 0 && s_sp[g * N + i] > 0);
+  const bool whole = G >= R;  // every configuration's slots in one pass
+  const int SP = whole ? G / R : 1;
+  E::build_nbt(s_nbt, whole ? SP * R : G, L, N);
+  for (int base = blockIdx.x * SP; base < B; base += gridDim.x * SP) {
+    const int Sb = min(SP, B - base);
+    if constexpr (!SYM) {
+      for (int idx = threadIdx.x; idx < Sb * N; idx += E::NTHR) s_sp[idx] = spins[(size_t)base * N + idx];
+      __syncthreads();
+      E::forward(theta, n_layers, s_sp, Sb, N, s_act, s_frag, s_nbt, s_lp);
+      for (int q = threadIdx.x; q < Sb; q += E::NTHR) out[base + q] = s_lp[q];
+    } else {
+      const int V = Sb * R;
+      for (int v0 = 0; v0 < V; v0 += G) {
+        const int Gb = min(G, V - v0);
+        for (int idx = threadIdx.x; idx < Gb * N; idx += E::NTHR) {
+          const int g = idx / N, i = idx - g * N, v = v0 + g, q = v / R;
+          s_sp[idx] = spins[(size_t)(base + q) * N + rot_src(i, v - q * R, L)];
         }
-        sign[base + g] = (marshall && (up & 1)) ? -1 : 1;
+        __syncthreads();
+        E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
+        if (whole) {
+          for (int q = threadIdx.x; q < Sb; q += E::NTHR) out[base + q] = lse(s_lp + q * R, R);
+        } else if (threadIdx.x == 0) {
+          double mx = v0 == 0 ? -INFINITY : s_run[0], t = v0 == 0 ? 0.0 : s_run[1];
+          for (int g = 0; g < Gb; ++g) {
+            const double v = s_lp[g], m2 = fmax(mx, v);
+            t = t * exp(mx - m2) + exp(v - m2);
+            mx = m2;
+          }
+          s_run[0] = mx;
+          s_run[1] = t;
+        }
+        __syncthreads();
+      }
+      if (!whole && threadIdx.x == 0) out[base] = s_run[0] + log(s_run[1]);
+    }
+    if (sign) {
+      // the Marshall sign of S (its rotations share it when Sz = 0)
+      for (int q = 0; q < Sb; ++q) {
+        const int8_t *sq = spins + (size_t)(base + q) * N;
+        int up = 0;
+        for (int i = threadIdx.x; i < N; i += E::NTHR) {
+          const int y = i / L, x = i - y * L;
+          up += (((x + y) & 1) == 0 && sq[i] > 0);
+        }
+        up = block_isum<NW>(up, s_ired);
+        if (threadIdx.x == 0) sign[base + q] = (marshall && (up & 1)) ? -1 : 1;
       }
     }
     __syncthreads();
@@ -140,7 +191,8 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const fl
                                                        int n_layers, double J1, double J2,
                                                        int marshall, int G,
                                                        double *__restrict__ e_loc,
-                                                       int32_t *__restrict__ flags) {
+                                                       int32_t *__restrict__ flags,
+                                                       double *__restrict__ lp_out) {
   using E = Engine<C, PREC, NW, TPW>;
   constexpr int MR = E::MAXROWS;
   __shared__ __align__(16) char s_act[E::ACT_BYTES];
@@ -224,6 +276,7 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const fl
     if (tid == 0) {
       e_loc[b] = eacc;
       if (flags) flags[b] = ((!isfinite(eacc) || !isfinite(lp0)) ? 1 : 0) | (sz != 0 ? 2 : 0) | (bad ? 4 : 0);
+      if (lp_out) lp_out[b] = lp0;
     }
     __syncthreads();
   }
@@ -233,18 +286,21 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const fl
 
 // One chain per workgroup (a single wavefront for small lattices).  Every
 // thread computes the same Philox words and reads the same LDS state, so all
-// control flow below is uniform across the workgroup.
+// control flow below is uniform across the workgroup.  With R = 4 the chain's
+// configuration is kept apart (s_cfg) and every evaluation fills the batch
+// with its four rotations, at most G of them per forward pass.
 template <int C, int PREC, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict__ theta,
                                                          int8_t *__restrict__ spins, int B, int L,
                                                          int n_layers, int n_sweeps, uint64_t seed,
-                                                         uint64_t counter_base, int proposal,
-                                                         double *__restrict__ log_psi,
+                                                         uint64_t counter_base, int proposal, int R,
+                                                         int G, double *__restrict__ log_psi,
                                                          int32_t *__restrict__ n_acc) {
   using E = Engine<C, PREC, NW, TPW>;
   __shared__ __align__(16) char s_act[E::ACT_BYTES];
   __shared__ __align__(16) char s_frag[E::FRAG_BYTES];
   __shared__ int8_t s_sp[E::MAXROWS];
+  __shared__ int8_t s_rot[E::MAXROWS];
   __shared__ double s_lp[64];
   __shared__ int s_ired[NW];
   __shared__ int s_pick[2];
@@ -253,11 +309,35 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
   const int N = L * L;
   const int b = blockIdx.x;
   int8_t *s = spins + (size_t)b * N;
-  E::build_nbt(s_nbt, 1, L, N);
-  for (int i = tid; i < N; i += E::NTHR) s_sp[i] = s[i];
+  int8_t *s_cfg = R == 1 ? s_sp : s_rot;  // the chain's configuration
+  E::build_nbt(s_nbt, R == 1 ? 1 : G, L, N);
+  // log|W| (or log|W~|) of the configuration in s_cfg; uniform result
+  // (one call site of the engine keeps the kernel's register budget)
+  auto evaluate = [&]() -> double {
+    double mx = -INFINITY, t = 0.0;
+    for (int r0 = 0; r0 < R; r0 += G) {
+      const int Gb = min(G, R - r0);
+      if (R > 1) {
+        for (int idx = tid; idx < Gb * N; idx += E::NTHR) {
+          const int g = idx / N, i = idx - g * N;
+          s_sp[idx] = s_cfg[rot_src(i, r0 + g, L)];
+        }
+        __syncthreads();
+      }
+      E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
+      if (R == 1) return s_lp[0];
+      for (int g = 0; g < Gb; ++g) {
+        const double v = s_lp[g], m2 = fmax(mx, v);
+        t = t * exp(mx - m2) + exp(v - m2);
+        mx = m2;
+      }
+      __syncthreads();
+    }
+    return mx + log(t);
+  };
+  for (int i = tid; i < N; i += E::NTHR) s_cfg[i] = s[i];
   __syncthreads();
-  E::forward(theta, n_layers, s_sp, 1, N, s_act, s_frag, s_nbt, s_lp);
-  double lp = s_lp[0];
+  double lp = evaluate();
   int acc = 0;
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   const int chunk = (2 * N + E::NTHR - 1) / E::NTHR;
@@ -272,13 +352,13 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
       int kind;
       const int k = (int)(((uint64_t)c0 * (uint64_t)(2 * N)) >> 32);
       decode_bond(k, L, N, i, j, kind);
-      if (s_sp[i] == s_sp[j]) continue;  // parallel pair: rejected move
+      if (s_cfg[i] == s_cfg[j]) continue;  // parallel pair: rejected move
     } else {
       int cnt = 0;
       for (int k = k0; k < k1; ++k) {
         int a, c, kind;
         decode_bond(k, L, N, a, c, kind);
-        cnt += (s_sp[a] != s_sp[c]);
+        cnt += (s_cfg[a] != s_cfg[c]);
       }
       int off = block_excl_scan<NW>(cnt, s_ired, &nap);
       if (nap == 0) continue;
@@ -288,7 +368,7 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
         for (int k = k0; k < k1; ++k) {
           int a, c, kind;
           decode_bond(k, L, N, a, c, kind);
-          if (s_sp[a] != s_sp[c]) {
+          if (s_cfg[a] != s_cfg[c]) {
             if (seen == pick) {
               s_pick[0] = a;
               s_pick[1] = c;
@@ -303,20 +383,19 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
     }
     __syncthreads();
     if (tid == 0) {
-      const int8_t v = s_sp[i];
-      s_sp[i] = s_sp[j];
-      s_sp[j] = v;
+      const int8_t v = s_cfg[i];
+      s_cfg[i] = s_cfg[j];
+      s_cfg[j] = v;
     }
     __syncthreads();
-    E::forward(theta, n_layers, s_sp, 1, N, s_act, s_frag, s_nbt, s_lp);
-    const double lpn = s_lp[0];
+    const double lpn = evaluate();
     double hast = 0.0;
     if (proposal == 1) {
       int cnt = 0;
       for (int k = k0; k < k1; ++k) {
         int a, c, kind;
         decode_bond(k, L, N, a, c, kind);
-        cnt += (s_sp[a] != s_sp[c]);
+        cnt += (s_cfg[a] != s_cfg[c]);
       }
       const int napn = block_isum<NW>(cnt, s_ired);
       hast = log((double)nap) - log((double)napn);
@@ -327,17 +406,55 @@ __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict
       ++acc;
     } else {
       if (tid == 0) {
-        const int8_t v = s_sp[i];
-        s_sp[i] = s_sp[j];
-        s_sp[j] = v;
+        const int8_t v = s_cfg[i];
+        s_cfg[i] = s_cfg[j];
+        s_cfg[j] = v;
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < N; i += E::NTHR) s[i] = s_sp[i];
+  for (int i = tid; i < N; i += E::NTHR) s[i] = s_cfg[i];
   if (tid == 0) {
     if (log_psi) log_psi[b] = lp;
     if (n_acc) n_acc[b] = acc;
+  }
+}
+
+// ------------------------------------------------- rotation-symmetrised E_s
+
+// rot[4b + r] = T^r spins[b] (Eq. sym-ws), one thread per output byte.
+__global__ void rotate_kernel(const int8_t *__restrict__ spins, int B, int L, int8_t *__restrict__ rot) {
+  const int N = L * L;
+  const int64_t total = (int64_t)4 * B * N;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = t / N;
+    const int i = (int)(t - v * N);
+    rot[t] = spins[(v >> 2) * N + rot_src(i, (int)(v & 3), L)];
+  }
+}
+
+// E_s = sum_r p_r E_CNN(T^r s), p_r = softmax_r log W_CNN(T^r s); the flags
+// of the four rotations are merged (bit 1 also for a non-finite result).
+__global__ void sym_combine_kernel(const double *__restrict__ e4, const double *__restrict__ lp4,
+                                   const int32_t *__restrict__ f4, int B, double *__restrict__ e_loc,
+                                   int32_t *__restrict__ flags) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double *l = lp4 + 4 * (size_t)b, *e = e4 + 4 * (size_t)b;
+  const double mx = fmax(fmax(l[0], l[1]), fmax(l[2], l[3]));
+  double z = 0.0, acc = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double w = exp(l[r] - mx);
+    z += w;
+    acc += w * e[r];
+  }
+  const double E = acc / z;
+  e_loc[b] = E;
+  if (flags) {
+    const int32_t *f = f4 + 4 * (size_t)b;
+    flags[b] = f[0] | f[1] | f[2] | f[3] | (isfinite(E) ? 0 : 1);
   }
 }
 
@@ -364,39 +481,51 @@ struct FwdArgs {
   int32_t *out_i;
   int n_sweeps, proposal;
   uint64_t seed, counter_base;
+  int R;           // 1, or 4 for the rotation-symmetrised amplitude
+  double *lp_out;  // local energy: log|W_CNN(s)| per sample (nullable)
   hipStream_t stream;
 };
 
 template <int C, int PREC>
 static vqmc_status launch(Kind kind, const FwdArgs &a) {
   using I = Inst<C>;
+  using E = Engine<C, PREC, I::NW, I::TPW>;
+  using ES = Engine<C, PREC, I::SNW, I::STPW>;
   const int N = a.L * a.L;
+  if (N > E::MAXROWS) return VQMC_ERR_SHAPE;
+  if (a.B == 0) return VQMC_OK;
   if (kind == K_SAMPLE) {
-    if (a.B == 0 || a.n_sweeps < 0) return VQMC_OK;
-    if (N <= Engine<C, PREC, I::SNW, I::STPW>::MAXROWS) {
+    if (a.n_sweeps < 0) return VQMC_OK;
+    // the small engine (one wavefront) when all R evaluations fit one batch
+    if (a.R * N <= ES::MAXROWS) {
       sample_kernel<C, PREC, I::SNW, I::STPW><<<a.B, I::SNW * 64, 0, a.stream>>>(
-          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal,
-          a.out_d, a.out_i);
+          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
+          a.R, a.out_d, a.out_i);
     } else {
+      const int G = min(a.R, E::MAXROWS / N);
       sample_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
-          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal,
-          a.out_d, a.out_i);
+          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
+          G, a.out_d, a.out_i);
     }
     VQMC_LAUNCH_CHECK();
     return VQMC_OK;
   }
-  using E = Engine<C, PREC, I::NW, I::TPW>;
-  if (N > E::MAXROWS) return VQMC_ERR_SHAPE;
   int G = E::MAXROWS / N;
   G = G > 64 ? 64 : G;
-  if (a.B == 0) return VQMC_OK;
   if (kind == K_LOGPSI) {
-    const int grid = (a.B + G - 1) / G;
-    logpsi_kernel<C, PREC, I::NW, I::TPW><<<grid, I::NW * 64, 0, a.stream>>>(
-        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.marshall, G, a.out_d, a.out_sign);
+    // whole configurations per workgroup: G rounded down to a multiple of R
+    if (G >= a.R) G -= G % a.R;
+    const int SP = a.R == 1 ? G : (G >= a.R ? G / a.R : 1);
+    const int grid = (a.B + SP - 1) / SP;
+    if (a.R == 1)
+      logpsi_kernel<C, PREC, I::NW, I::TPW, false><<<grid, I::NW * 64, 0, a.stream>>>(
+          a.theta, a.spins_in, a.B, a.L, a.n_layers, a.marshall, G, a.out_d, a.out_sign);
+    else
+      logpsi_kernel<C, PREC, I::NW, I::TPW, true><<<grid, I::NW * 64, 0, a.stream>>>(
+          a.theta, a.spins_in, a.B, a.L, a.n_layers, a.marshall, G, a.out_d, a.out_sign);
   } else {
     eloc_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
-        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i);
+        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i, a.lp_out);
   }
   VQMC_LAUNCH_CHECK();
   return VQMC_OK;
@@ -437,6 +566,7 @@ extern "C" vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta, con
   a.marshall = m->marshall;
   a.out_d = log_abs_psi;
   a.out_sign = sign;
+  a.R = m->symmetry ? 4 : 1;
   a.stream = stream;
   return dispatch(K_LOGPSI, m->channels, m->conv_prec, a);
 }
@@ -448,25 +578,35 @@ static bool use_lightcone(const vqmc_model *m) {
   return m->eloc_mode == VQMC_ELOC_LIGHTCONE || m->L >= 14;
 }
 
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Symmetrised local energy: rotated copies, per-rotation E and log|W_CNN|,
+// flags, then the workspace of the inner evaluation of 4B configurations.
+static size_t sym_head_bytes(const vqmc_model *m, int B) {
+  const size_t V = (size_t)4 * B, N = (size_t)m->L * m->L;
+  return al256(V * N) + 2 * al256(V * 8) + al256(V * 4);
+}
+
+static size_t eloc_ws_bytes(const vqmc_model *m, int B) {
+  if (!m->symmetry) return use_lightcone(m) ? eloc_lc_workspace(m, B) : 0;
+  return sym_head_bytes(m, B) + (use_lightcone(m) ? eloc_lc_workspace(m, 4 * B) : 0);
+}
+
 extern "C" vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes) {
   if (!model_valid(m) || !bytes) return VQMC_ERR_ARG;
-  if (B < 0) return VQMC_ERR_SHAPE;
+  if (B < 0 || (m->symmetry && B > INT32_MAX / 4)) return VQMC_ERR_SHAPE;
   if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
-  *bytes = use_lightcone(m) ? eloc_lc_workspace(m, B) : 0;
+  *bytes = eloc_ws_bytes(m, B);
   return VQMC_OK;
 }
 
-extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
-                                         const int8_t *spins, int32_t B, double *e_loc,
-                                         int32_t *chain_flags, void *workspace, size_t ws_bytes,
-                                         hipStream_t stream) {
-  if (!model_valid(m)) return VQMC_ERR_ARG;
-  if (B < 0) return VQMC_ERR_SHAPE;
-  if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
-  if (B > 0 && (!theta || !spins || !e_loc)) return VQMC_ERR_ARG;
-  if (B > 0 && use_lightcone(m)) {
-    if (!workspace || ws_bytes < eloc_lc_workspace(m, B)) return VQMC_ERR_WORKSPACE;
-    return eloc_lc(m, theta, spins, B, e_loc, chain_flags, workspace, stream);
+// The unsymmetrised evaluation of B configurations (dense or light cone).
+static vqmc_status eloc_plain(const vqmc_model *m, const float *theta, const int8_t *spins, int32_t B,
+                              double *e_loc, int32_t *flags, double *lp, void *ws, size_t ws_bytes,
+                              hipStream_t stream) {
+  if (use_lightcone(m)) {
+    if (!ws || ws_bytes < eloc_lc_workspace(m, B)) return VQMC_ERR_WORKSPACE;
+    return eloc_lc(m, theta, spins, B, e_loc, flags, lp, ws, stream);
   }
   FwdArgs a{};
   a.theta = theta;
@@ -478,9 +618,45 @@ extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta
   a.J1 = m->J1;
   a.J2 = m->J2;
   a.out_d = e_loc;
-  a.out_i = chain_flags;
+  a.out_i = flags;
+  a.R = 1;
+  a.lp_out = lp;
   a.stream = stream;
   return dispatch(K_ELOC, m->channels, m->conv_prec, a);
+}
+
+extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
+                                         const int8_t *spins, int32_t B, double *e_loc,
+                                         int32_t *chain_flags, void *workspace, size_t ws_bytes,
+                                         hipStream_t stream) {
+  if (!model_valid(m)) return VQMC_ERR_ARG;
+  if (B < 0 || (m->symmetry && B > INT32_MAX / 4)) return VQMC_ERR_SHAPE;
+  if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
+  if (B > 0 && (!theta || !spins || !e_loc)) return VQMC_ERR_ARG;
+  if (!m->symmetry) {
+    if (B == 0 && use_lightcone(m)) return VQMC_OK;
+    return eloc_plain(m, theta, spins, B, e_loc, chain_flags, nullptr, workspace, ws_bytes, stream);
+  }
+  const int N = m->L * m->L;
+  if (B == 0) return VQMC_OK;
+  if (!workspace || ws_bytes < eloc_ws_bytes(m, B)) return VQMC_ERR_WORKSPACE;
+  char *w = reinterpret_cast<char *>(workspace);
+  const size_t V = (size_t)4 * B;
+  int8_t *rot = reinterpret_cast<int8_t *>(w);
+  double *e4 = reinterpret_cast<double *>(w + al256(V * N));
+  double *lp4 = reinterpret_cast<double *>(w + al256(V * N) + al256(V * 8));
+  int32_t *f4 = reinterpret_cast<int32_t *>(w + al256(V * N) + 2 * al256(V * 8));
+  char *inner = w + sym_head_bytes(m, B);
+  const int64_t total = (int64_t)V * N;
+  const int blocks = (int)((total + 255) / 256 < 8192 ? (total + 255) / 256 : 8192);
+  rotate_kernel<<<blocks, 256, 0, stream>>>(spins, B, m->L, rot);
+  VQMC_LAUNCH_CHECK();
+  const vqmc_status st = eloc_plain(m, theta, rot, (int32_t)V, e4, f4, lp4, inner,
+                                    ws_bytes - sym_head_bytes(m, B), stream);
+  if (st != VQMC_OK) return st;
+  sym_combine_kernel<<<(B + 255) / 256, 256, 0, stream>>>(e4, lp4, f4, B, e_loc, chain_flags);
+  VQMC_LAUNCH_CHECK();
+  return VQMC_OK;
 }
 
 extern "C" vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8_t *spins,
@@ -504,6 +680,7 @@ extern "C" vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8
   a.proposal = proposal;
   a.seed = seed;
   a.counter_base = counter_base;
+  a.R = m->symmetry ? 4 : 1;
   a.stream = stream;
   return dispatch(K_SAMPLE, m->channels, m->conv_prec, a);
 }

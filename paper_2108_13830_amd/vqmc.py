@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import dataclasses
 from dataclasses import dataclass
 
 import torch
@@ -38,7 +39,8 @@ class VqmcError(RuntimeError):
 class _Model(ct.Structure):
     _fields_ = [("L", ct.c_int32), ("channels", ct.c_int32), ("n_layers", ct.c_int32),
                 ("activation", ct.c_int32), ("J1", ct.c_double), ("J2", ct.c_double),
-                ("marshall", ct.c_int32), ("conv_prec", ct.c_int32), ("eloc_mode", ct.c_int32)]
+                ("marshall", ct.c_int32), ("conv_prec", ct.c_int32), ("eloc_mode", ct.c_int32),
+                ("symmetry", ct.c_int32)]
 
 
 class _SrOpts(ct.Structure):
@@ -54,7 +56,8 @@ class _SrInfo(ct.Structure):
 @dataclass(frozen=True)
 class Model:
     """Lattice L x L, C channels, n C->C layers after the lift, couplings,
-    Marshall sign on/off and the precision of the forward convolutions."""
+    Marshall sign on/off, the precision of the forward convolutions, the
+    local-energy method and the rotation symmetrisation on/off."""
     L: int
     C: int
     n: int
@@ -63,16 +66,21 @@ class Model:
     marshall: int = 1
     prec: int = PREC_FP32
     eloc: int = ELOC_AUTO
+    symmetry: int = 0
 
     def c(self) -> _Model:
-        return _Model(self.L, self.C, self.n, 0, self.J1, self.J2, self.marshall, self.prec, self.eloc)
+        return _Model(self.L, self.C, self.n, 0, self.J1, self.J2, self.marshall, self.prec, self.eloc,
+                      self.symmetry)
 
     def with_prec(self, prec) -> "Model":
         p = PREC_NAMES[prec] if isinstance(prec, str) else prec
-        return Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, p, self.eloc)
+        return dataclasses.replace(self, prec=p)
 
     def with_eloc(self, eloc) -> "Model":
-        return Model(self.L, self.C, self.n, self.J1, self.J2, self.marshall, self.prec, eloc)
+        return dataclasses.replace(self, eloc=eloc)
+
+    def with_symmetry(self, symmetry: int = 1) -> "Model":
+        return dataclasses.replace(self, symmetry=symmetry)
 
     @property
     def N(self) -> int:

@@ -15,9 +15,10 @@ from paper_2108_13830_amd import vqmc as V  # noqa: E402
 DEV = "cuda:0"
 
 
-def models(L, C, n, prec=V.PREC_FP32, J1=1.0, J2=0.5, marshall=1):
+def models(L, C, n, prec=V.PREC_FP32, J1=1.0, J2=0.5, marshall=1, symmetry=0, eloc=V.ELOC_AUTO):
     """The same model for the GPU library and for the oracle."""
-    return V.Model(L, C, n, J1, J2, marshall, prec), R.RefModel(L, C, n, J1, J2, marshall)
+    return (V.Model(L, C, n, J1, J2, marshall, prec, eloc, symmetry),
+            R.RefModel(L, C, n, J1, J2, marshall, symmetry=symmetry))
 
 
 def to_dev(a, dtype=None):

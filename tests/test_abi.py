@@ -37,7 +37,8 @@ def test_num_params_and_model_validation():
     assert V.num_params(V.Model(24, 32, 8)) == 74304
     for bad in (V.Model(5, 4, 2), V.Model(26, 4, 2), V.Model(4, 12, 2), V.Model(4, 4, 0),
                 V.Model(4, 4, 2, eloc=3),
-                V.Model(4, 4, 2, prec=V.PREC_BF16), V.Model(4, 8, 2, prec=7), V.Model(4, 8, 2, marshall=2)):
+                V.Model(4, 4, 2, prec=V.PREC_BF16), V.Model(4, 8, 2, prec=7), V.Model(4, 8, 2, marshall=2),
+                V.Model(4, 4, 2, symmetry=2)):
         assert V.num_params(bad) == -1
 
 
@@ -70,6 +71,21 @@ def test_argument_errors_need_no_gpu():
     assert lib.vqmc_local_energy_workspace(ct.byref(lc4), 64, ct.byref(n)) == 1
     dense = V.Model(16, 32, 8, eloc=V.ELOC_DENSE).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 0
+    # the symmetrised local energy needs a workspace for its 4B rotated copies
+    sym = V.Model(10, 16, 6, eloc=V.ELOC_DENSE, symmetry=1).c()
+    assert lib.vqmc_local_energy_workspace(ct.byref(sym), 64, ct.byref(n)) == 0
+    assert n.value >= 4 * 64 * 100 + 4 * 64 * (8 + 8 + 4)
+    assert lib.vqmc_local_energy(ct.byref(sym), ct.c_void_p(8), ct.c_void_p(8), 64, ct.c_void_p(8), nul,
+                                 nul, 0, nul) == 4
+    assert lib.vqmc_local_energy(ct.byref(sym), nul, nul, 0, nul, nul, nul, 0, nul) == 0
+    symlc = V.Model(16, 32, 8, eloc=V.ELOC_LIGHTCONE, symmetry=1).c()
+    m = ct.c_size_t(0)
+    assert lib.vqmc_local_energy_workspace(ct.byref(lc), 256, ct.byref(n)) == 0
+    assert lib.vqmc_local_energy_workspace(ct.byref(symlc), 64, ct.byref(m)) == 0 and m.value > n.value
+    # a 24 x 24 lattice does not fit the 512-row engine of C <= 16 (dense and sampler)
+    big16 = V.Model(24, 16, 2, eloc=V.ELOC_DENSE).c()
+    assert lib.vqmc_log_psi(ct.byref(big16), ct.c_void_p(8), ct.c_void_p(8), 1, ct.c_void_p(8), nul, nul) == 2
+    assert lib.vqmc_sample(ct.byref(big16), ct.c_void_p(8), ct.c_void_p(8), nul, 1, 1, 0, 0, 0, nul, nul) == 2
     assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 2, 1, 0, 0, 5, nul, nul) == 1
     assert lib.vqmc_sample(ct.byref(good), nul, nul, nul, 0, 1, 0, 0, 0, nul, nul) == 0
     n = ct.c_size_t(0)
