@@ -67,9 +67,13 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
 
 WORKLOADS = {
     "10x10": dict(L=10, C=16, n=6, B=4096, spins="sampled", sr="chol32"),
-    "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="cg"),
-    "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="cg"),
+    "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="dual"),
+    "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="dual"),
 }
+
+
+SR_NAMES = {"chol32": "Cholesky of S, S on FP32 matrix cores", "chol64": "Cholesky of S, S in FP64",
+            "dual": "Cholesky of the B x B sample-space matrix, FP64", "cg": "CG, tol 1e-8, at most 200 iterations"}
 
 
 def sr_opts(V, name):
@@ -147,7 +151,9 @@ def copy_calibration(mib):
 def other_workload(V, torch, name, convs):
     """One full step of another workload (uniform Sz = 0 configurations) per
     convolution form: samples/s and stage times, for the second lattice the
-    metric names.  One warm-up step, one timed step per form."""
+    metric names.  One warm-up step, one timed step per form; then the
+    matrix-free CG solve of the same system (tol 1e-8, at most 200
+    iterations), timed on its own."""
     from vqmc_inputs import init_theta, uniform_sz0
     wl = WORKLOADS[name]
     L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
@@ -156,13 +162,13 @@ def other_workload(V, torch, name, convs):
     spins = torch.from_numpy(uniform_sz0(L, B, seed=1)).to(dev)
     spins_np = spins.cpu().numpy()
     res = {"workload": "%s periodic J1-J2 (J2/J1=0.5), C=%d, n=%d, B=%d uniform Sz=0 configurations; "
-                       "E_loc (light cone) + O_k + SR (CG, tol 1e-8, at most 200 iterations)" % (name, C, n, B)}
+                       "E_loc (light cone) + O_k + SR (exact, %s)" % (name, C, n, B, SR_NAMES[wl["sr"]])}
     base = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_FP32, V.ELOC_AUTO)
     P = V.num_params(base)
     O = torch.empty((B, P), dtype=torch.float32, device=dev)
     e = torch.empty(B, dtype=torch.float64, device=dev)
     ws_o = torch.empty(max(V.log_derivs_workspace(base, B), 1), dtype=torch.uint8, device=dev)
-    opts = sr_opts(V, "cg")
+    opts = sr_opts(V, wl["sr"])
     ws_sr = torch.empty(max(V.sr_workspace(B, P, opts), 1), dtype=torch.uint8, device=dev)
     delta = torch.empty(P, dtype=torch.float64, device=dev)
     for conv in convs:
@@ -170,7 +176,6 @@ def other_workload(V, torch, name, convs):
         lightcone = V.local_energy_workspace(gm, 1) > 0
         nb = V.local_energy_workspace(gm, B)
         ws_e = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
-        info = None
         for it in range(2):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             torch.cuda.synchronize()
@@ -180,7 +185,7 @@ def other_workload(V, torch, name, convs):
             ev[1].record()
             V.vqmc_log_derivs(base, th, spins, O=O, workspace=ws_o)
             ev[2].record()
-            _, _, info = V.vqmc_sr_solve(O, e, opts, delta=delta, workspace=ws_sr)
+            V.vqmc_sr_solve(O, e, opts, delta=delta, workspace=ws_sr, want_info=False)
             ev[3].record()
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -190,10 +195,26 @@ def other_workload(V, torch, name, convs):
                      "stage_ms": {"local_energy": st[0], "log_derivs": st[1], "sr_solve": st[2]},
                      "eloc": "lightcone" if lightcone else "dense",
                      "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
-                     "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12,
-                     "cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
-                     "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9}
+                     "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12}
+        if wl["sr"] == "dual":
+            # lower half of the B x B Gram matrix: B^2 P FLOPs (FP64 matrix cores)
+            res[conv]["gram_tflop"] = B * B * P / 1e12
         del ws_e
+    # matrix-free CG on the last O, e (each iteration streams O twice)
+    del ws_sr
+    oc = sr_opts(V, "cg")
+    ws_c = torch.empty(max(V.sr_workspace(B, P, oc), 1), dtype=torch.uint8, device=dev)
+    for it in range(2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        _, _, info = V.vqmc_sr_solve(O, e, oc, delta=delta, workspace=ws_c)
+        ev[1].record()
+        torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    res["sr_cg"] = {"sr_solve_ms": ms, "cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
+                    "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (ms / 1e3) / 1e9}
+    del ws_c
     return res
 
 
@@ -210,7 +231,7 @@ def main():
     ap.add_argument("--burn-in", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual",
+    ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual,sym",
                     help="extra forms timed on the same inputs (comma list, or 'none')")
     ap.add_argument("--also", default="24x24",
                     help="another workload timed after the main one (one step per form, bf16x3 and fp32), "
@@ -283,7 +304,7 @@ def main():
         V.vqmc_local_energy(model, th, spins, out=e, workspace=eloc_ws(model))
         if ev:
             ev[1].record()
-        V.vqmc_log_derivs(gm.with_prec("fp32"), th, spins, O=O, workspace=ws_o)
+        V.vqmc_log_derivs(model.with_prec("fp32"), th, spins, O=O, workspace=ws_o)
         if ev:
             ev[2].record()
         V.vqmc_sr_solve(O, e, o, delta=delta, F=F, workspace=ws, want_info=False)
@@ -355,6 +376,13 @@ def main():
                 variants["eloc_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
                                          "stage_ms": vst.tolist(),
                                          "eloc_tflops_algorithmic": fa / (vst[0] / 1e3) / 1e12}
+            elif v == "sym":
+                # the rotation-symmetrised amplitude: four turned configurations
+                # per sample in E_loc and O_k (same SR)
+                vms, vst = timed(gm.with_symmetry(1), opts, ws_sr, 1, 1)
+                variants["sym"] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
+                                   "stage_ms": vst.tolist(),
+                                   "eloc_tflops_algorithmic": 4 * flops_eloc / (vst[0] / 1e3) / 1e12}
             elif v in ("chol32", "chol64", "dual", "cg") and v != sr_name:
                 vo = sr_opts(V, v)
                 vws = torch.empty(max(V.sr_workspace(B, P, vo), 1), dtype=torch.uint8, device=dev)

@@ -176,9 +176,12 @@ vqmc_status vqmc_log_derivs(const vqmc_model *m, const float *theta,
                             void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /* Options of the SR solve (Sec. 3.2.2).
- *   method   0 auto (P <= 16384: Cholesky, else CG), 1 Cholesky of the
- *            explicit P x P matrix, 2 matrix-free conjugate gradients,
- *            3 Cholesky of the equivalent B x B sample-space matrix;
+ *   method   0 auto: the smaller of the two exact forms (B < P: method 3,
+ *            else method 1) while its order is at most 65536, else CG;
+ *            1 Cholesky of the explicit P x P matrix, 2 matrix-free
+ *            conjugate gradients, 3 Cholesky of the equivalent B x B
+ *            sample-space matrix (the same delta, by the push-through
+ *            identity Oc^T (Oc Oc^T/B + eps I)^-1 = (Oc^T Oc/B + eps I)^-1 Oc^T);
  *   s_prec   (method 1) 0: S accumulated by FP32 matrix cores from FP32
  *            centred O; 1: FP64 accumulation (FP64 matrix cores);
  *   eps      diagonal shift (> 0);

@@ -521,7 +521,14 @@ struct SrPlan {
 
 static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
   SrPlan s{};
-  s.method = o->method == 0 ? (P <= 16384 ? 1 : 2) : o->method;
+  if (o->method == 0) {
+    // the smaller exact form while its matrix stays within order 65536
+    constexpr int64_t kMaxExact = 65536;
+    if (B < P) s.method = B <= kMaxExact ? 3 : 2;
+    else s.method = P <= kMaxExact ? 1 : 2;
+  } else {
+    s.method = o->method;
+  }
   const int64_t colblocks = (P + 1023) / 1024;  // column blocks of the 4-wide column pass
   int nch = (int)((4096 + colblocks - 1) / colblocks);
   nch = nch < 1 ? 1 : (nch > 64 ? 64 : nch);

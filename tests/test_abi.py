@@ -99,8 +99,14 @@ def test_sr_argument_errors_and_workspace():
     lib = V.lib()
     n = ct.c_size_t(0)
     ok = V.SrOpts().c()
+    # auto: the smaller exact form
     assert lib.vqmc_sr_workspace(4096, 14080, ct.byref(ok), ct.byref(n)) == 0
+    assert 4096 * 4096 * 8 <= n.value < 14080 * 14080 * 8  # the sample-space matrix
+    assert lib.vqmc_sr_workspace(20000, 14080, ct.byref(ok), ct.byref(n)) == 0
     assert n.value >= 14080 * 14080 * 8  # the explicit S matrix
+    ch = V.SrOpts(method=V.SR_CHOLESKY).c()
+    assert lib.vqmc_sr_workspace(4096, 14080, ct.byref(ch), ct.byref(n)) == 0
+    assert n.value >= 14080 * 14080 * 8
     cg = V.SrOpts(method=V.SR_CG).c()
     assert lib.vqmc_sr_workspace(16384, 74304, ct.byref(cg), ct.byref(n)) == 0
     assert n.value < 74304 * 74304 * 8 // 100  # matrix-free

@@ -80,6 +80,13 @@ def test_24x24_full_batch_log_derivs_and_cg():
     # the rounding of up to 200 FP64 iterations, and CG has reduced it
     assert abs(rr - info["rel_residual"]) <= 1e-6 + 1e-3 * info["rel_residual"]
     assert rr < 0.5
+    # the exact solve of the same system through the B x B sample-space matrix
+    announce("24x24 full batch sample-space solve")
+    dd, Fd, _ = V.vqmc_sr_solve(O, e, V.SrOpts(method=V.SR_DUAL, eps=1e-4))
+    rd = _residual(O, e, dd, 1e-4)
+    print("24x24 sample-space solve recomputed residual %.3e" % rd)
+    assert rd <= 1e-8
+    np.testing.assert_allclose(host(Fd), host(F), rtol=1e-12, atol=1e-14 * float(F.abs().max()))
 
 
 def test_10x10_full_batch_sampled_against_oracle():
