@@ -219,6 +219,35 @@ vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *e_loc,
                           double *delta, double *F, void *workspace,
                           size_t ws_bytes, vqmc_sr_info *info, hipStream_t stream);
 
+/* One iteration of the optimisation loop (Sec. 3.1 and 3.2, Fig. framework):
+ *   Step 1: n_sweeps sweeps of vqmc_sample on the B chains, in place, from
+ *           where the previous iteration left them (proposal, seed and
+ *           counters as there: this call uses counters counter_base ..
+ *           counter_base + n_sweeps*N - 1, so the caller advances
+ *           counter_base by n_sweeps*N per call);
+ *   Step 2: E_s (vqmc_local_energy), O_s (vqmc_log_derivs, FP32), the SR
+ *           solve (S + eps I) delta = F with options sr, and the update
+ *           theta <- theta - lr * delta (FP64 arithmetic, rounded once to
+ *           FP32), in place on theta.
+ * e_loc (dev double [B], nullable) receives the local energies of the
+ * sampled configurations (under the theta the call started with).  info
+ * (host, nullable) receives their mean and variance and the SR report, and
+ * forces a stream synchronisation; only then is a failed factorisation
+ * (VQMC_ERR_NOT_SPD, theta left unchanged) detected.  With CG that reaches
+ * max_iter the update uses the last iterate and VQMC_WARN_NOT_CONVERGED is
+ * returned.  workspace: dev, vqmc_vmc_step_workspace bytes (E_s, O, delta
+ * and the three inner workspaces).  B >= 2, n_sweeps >= 0. */
+vqmc_status vqmc_vmc_step(const vqmc_model *m, float *theta, int8_t *spins,
+                          int32_t B, int32_t n_sweeps, uint64_t seed,
+                          uint64_t counter_base, int32_t proposal,
+                          const vqmc_sr_opts *sr, double lr, double *e_loc,
+                          void *workspace, size_t ws_bytes, vqmc_sr_info *info,
+                          hipStream_t stream);
+
+/* Workspace (device bytes) of vqmc_vmc_step for this model, B and solver. */
+vqmc_status vqmc_vmc_step_workspace(const vqmc_model *m, int32_t B,
+                                    const vqmc_sr_opts *sr, size_t *bytes);
+
 #ifdef __cplusplus
 }
 #endif

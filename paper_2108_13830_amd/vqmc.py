@@ -122,6 +122,11 @@ SIGNATURES = [
     ("vqmc_sr_solve", ct.c_int, [_VP, ct.c_int64, _VP, ct.c_int32, ct.c_int64,
                                  ct.POINTER(_SrOpts), _VP, _VP, _VP, ct.c_size_t,
                                  ct.POINTER(_SrInfo), _VP]),
+    ("vqmc_vmc_step", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, ct.c_int32, ct.c_uint64,
+                                 ct.c_uint64, ct.c_int32, ct.POINTER(_SrOpts), ct.c_double, _VP, _VP,
+                                 ct.c_size_t, ct.POINTER(_SrInfo), _VP]),
+    ("vqmc_vmc_step_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32, ct.POINTER(_SrOpts),
+                                           ct.POINTER(ct.c_size_t)]),
 ]
 
 
@@ -298,6 +303,39 @@ def vqmc_sr_solve(O, e_loc, opts: SrOpts = SrOpts(), P: int | None = None, delta
         d = dict(e_mean=info.e_mean, e_var=info.e_var, iters=info.iters,
                  rel_residual=info.rel_residual, converged=(rc == 0))
     return delta, F, d
+
+
+def vmc_step_workspace(m: Model, B: int, opts: SrOpts) -> int:
+    mc, oc = m.c(), opts.c()
+    n = ct.c_size_t(0)
+    _check("vqmc_vmc_step_workspace", lib().vqmc_vmc_step_workspace(ct.byref(mc), B, ct.byref(oc),
+                                                                    ct.byref(n)))
+    return n.value
+
+
+def vqmc_vmc_step(m: Model, theta, spins, n_sweeps: int, seed: int, counter_base: int, lr: float,
+                  opts: SrOpts = SrOpts(), proposal: int = 0, e_loc=None, workspace=None,
+                  want_info: bool = True):
+    """One optimisation iteration in place on theta and spins: sampling,
+    E_s, O_s, the SR solve and theta -= lr * delta.  Returns the info dict
+    (energy mean/variance, SR report) or None."""
+    B = spins.shape[0]
+    _dev(theta, torch.float32, "theta", (num_params(m),))
+    _dev(spins, torch.int8, "spins", (B, m.N))
+    _dev(e_loc, torch.float64, "e_loc", (B,))
+    ws = vmc_step_workspace(m, B, opts)
+    if workspace is None:
+        workspace = torch.empty(max(ws, 1), dtype=torch.uint8, device=spins.device)
+    mc, oc = m.c(), opts.c()
+    info = _SrInfo()
+    rc = lib().vqmc_vmc_step(ct.byref(mc), _ptr(theta), _ptr(spins), B, n_sweeps, seed & (2**64 - 1),
+                             counter_base, proposal, ct.byref(oc), lr, _ptr(e_loc), _ptr(workspace),
+                             workspace.numel(), ct.byref(info) if want_info else None, _stream())
+    _check("vqmc_vmc_step", rc, allow=(WARN_NOT_CONVERGED,))
+    if not want_info:
+        return None
+    return dict(e_mean=info.e_mean, e_var=info.e_var, iters=info.iters, rel_residual=info.rel_residual,
+                converged=(rc == 0))
 
 
 class LogPsi(torch.autograd.Function):
