@@ -447,9 +447,8 @@ __global__ void pack_lc_kernel(const float *__restrict__ theta, int n_layers, ch
     const int nt = r2 >> 6, ln = r2 & 63;
     const int n = nt * 16 + (ln & 15);
     const float *W = theta + layer_offset(C, l);
-    char *dst = out + (size_t)t * E::FRAG;
     if constexpr (PREC == P_F32) {
-      *reinterpret_cast<float *>(dst) = E::wsel(W, 4 * s + (ln >> 4), n);
+      reinterpret_cast<float *>(out)[t] = E::wsel(W, 4 * s + (ln >> 4), n);
     } else {
       const int k0 = 32 * s + 8 * (ln >> 4);
       u16x8 hi, lo;
@@ -459,8 +458,8 @@ __global__ void pack_lc_kernel(const float *__restrict__ theta, int n_layers, ch
         hi[j] = bf16_rne(w);
         lo[j] = bf16_rne(w - bf16_f32(hi[j]));
       }
-      reinterpret_cast<u16x8 *>(dst)[0] = hi;
-      if constexpr (PREC == P_X3) reinterpret_cast<u16x8 *>(dst)[1] = lo;
+      reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 0)] = hi;
+      if constexpr (PREC == P_X3) reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 1)] = lo;
     }
   }
 }

@@ -90,6 +90,12 @@ struct Engine {
   static constexpr int KS = (9 * C + KSTEP - 1) / KSTEP;
   static constexpr int LDA = F32 ? C + 1 : C;  // FP32 rows padded by one word
   static constexpr int FRAG = F32 ? 4 : (X3 ? 32 : 16);
+  // BF16 fragments are stored as 16-byte pieces in [block][part][lane] order
+  // (block = idx / 64 of the lane-order index idx, part 0 = hi, 1 = lo), so
+  // that the 64 lanes of a wave read one part as 1 KiB of consecutive bytes.
+  __host__ __device__ static constexpr int frag_piece(int idx, int part) {
+    return ((idx >> 6) * (FRAG / 16) + part) * 64 + (idx & 63);
+  }
   static constexpr int NTHR = NW * 64;
   static constexpr int MAXROWS = NW * TPW * 16;
   // FP32: padded rows; BF16 forms: hi (and lo) planes.  At least
@@ -134,25 +140,53 @@ struct Engine {
     return TRANSPOSED ? W[(ci * C + n) * 9 + tap] : W[(n * C + ci) * 9 + tap];
   }
 
-  template <bool TRANSPOSED = false>
+  // Stages W_l (theta order W[co][ci][tap], 9C^2 floats) in the fragment
+  // order above: the reads are coalesced (thread t takes elements t,
+  // t + NTHR, ...) and each element is scattered to its slot; the K padding
+  // of the BF16 forms (k in [9C, 32 KS)) and, for C < 16, the columns
+  // [C, 16) are written as zeros by slots of their own, so no slot is
+  // written twice.
   __device__ static __forceinline__ void stage_weights(const float *__restrict__ W, char *frag) {
-    for (int idx = threadIdx.x; idx < KS * NT * 64; idx += NTHR) {
-      const int s = idx / (NT * 64), rem = idx - s * (NT * 64);
-      const int nt = rem >> 6, ln = rem & 63;
-      const int n = nt * 16 + (ln & 15);
+    constexpr int WN = 9 * C * C;
+    for (int idx = threadIdx.x; idx < WN; idx += NTHR) {
+      const float w = W[idx];
+      const int n = idx / (9 * C), rem = idx - n * (9 * C), ci = rem / 9, tap = rem - ci * 9;
+      const int k = tap * C + ci, nt = n >> 4;
       if constexpr (F32) {
-        reinterpret_cast<float *>(frag)[idx] = wsel<TRANSPOSED>(W, 4 * s + (ln >> 4), n);
+        reinterpret_cast<float *>(frag)[((k >> 2) * NT + nt) * 64 + (k & 3) * 16 + (n & 15)] = w;
       } else {
-        const int k0 = 32 * s + 8 * (ln >> 4);
-        u16x8 hi, lo;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const float w = wsel<TRANSPOSED>(W, k0 + j, n);
-          hi[j] = bf16_rne(w);
-          lo[j] = bf16_rne(w - bf16_f32(hi[j]));
+        const int kk = k & 31;
+        const int piece = frag_piece(((k >> 5) * NT + nt) * 64 + (kk >> 3) * 16 + (n & 15), 0);
+        uint16_t *f = reinterpret_cast<uint16_t *>(frag);
+        const uint16_t hi = bf16_rne(w);
+        f[piece * 8 + (kk & 7)] = hi;
+        if constexpr (X3) f[(piece + 64) * 8 + (kk & 7)] = bf16_rne(w - bf16_f32(hi));
+      }
+    }
+    if constexpr (C < 16) {
+      // columns n in [C, 16) of the one 16-wide output tile are zero
+      constexpr int KT = KS * (F32 ? 4 : 32), NP = 16 - C;
+      for (int p = threadIdx.x; p < KT * NP; p += NTHR) {
+        const int k = p / NP, n = C + (p - (p / NP) * NP);
+        if constexpr (F32) {
+          reinterpret_cast<float *>(frag)[(k >> 2) * 64 + (k & 3) * 16 + n] = 0.f;
+        } else {
+          const int kk = k & 31;
+          const int piece = frag_piece((k >> 5) * 64 + (kk >> 3) * 16 + n, 0);
+          uint16_t *f = reinterpret_cast<uint16_t *>(frag);
+          f[piece * 8 + (kk & 7)] = 0;
+          if constexpr (X3) f[(piece + 64) * 8 + (kk & 7)] = 0;
         }
-        reinterpret_cast<u16x8 *>(frag + (size_t)idx * FRAG)[0] = hi;
-        if constexpr (X3) reinterpret_cast<u16x8 *>(frag + (size_t)idx * FRAG)[1] = lo;
+      }
+    }
+    if constexpr (!F32) {
+      constexpr int PADK = 32 * KS - 9 * C;  // zero rows of the last K-step
+      for (int p = threadIdx.x; p < PADK * C; p += NTHR) {
+        const int k = 9 * C + p / C, n = p - (p / C) * C, kk = k & 31, nt = n >> 4;
+        const int piece = frag_piece(((k >> 5) * NT + nt) * 64 + (kk >> 3) * 16 + (n & 15), 0);
+        uint16_t *f = reinterpret_cast<uint16_t *>(frag);
+        f[piece * 8 + (kk & 7)] = 0;
+        if constexpr (X3) f[(piece + 64) * 8 + (kk & 7)] = 0;
       }
     }
   }
@@ -253,9 +287,9 @@ struct Engine {
         u16x8 bh[NT], bl[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag + (size_t)((s * NT + nt) * 64 + lane) * FRAG);
+          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag) + frag_piece((s * NT + nt) * 64 + lane, 0);
           bh[nt] = f[0];
-          if constexpr (X3) bl[nt] = f[1];
+          if constexpr (X3) bl[nt] = f[64];
         }
         const int k0 = 32 * s + 8 * (lane >> 4);
         const bool kv = k0 < 9 * C;
@@ -388,9 +422,9 @@ struct Engine {
         u16x8 bh[NT], bl[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag + (size_t)((s * NT + nt) * 64 + lane) * FRAG);
+          const u16x8 *f = reinterpret_cast<const u16x8 *>(frag) + frag_piece((s * NT + nt) * 64 + lane, 0);
           bh[nt] = f[0];
-          if constexpr (X3) bl[nt] = f[1];
+          if constexpr (X3) bl[nt] = f[64];
         }
         const int k0 = 32 * s + 8 * (lane >> 4);
         const bool kv = k0 < 9 * C;
