@@ -67,8 +67,8 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
 
 WORKLOADS = {
     "10x10": dict(L=10, C=16, n=6, B=4096, spins="sampled", sr="chol32"),
-    "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="dual"),
-    "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="dual"),
+    "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="cg"),
+    "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="cg"),
 }
 
 
@@ -151,9 +151,9 @@ def copy_calibration(mib):
 def other_workload(V, torch, name, convs):
     """One full step of another workload (uniform Sz = 0 configurations) per
     convolution form: samples/s and stage times, for the second lattice the
-    metric names.  One warm-up step, one timed step per form; then the
-    matrix-free CG solve of the same system (tol 1e-8, at most 200
-    iterations), timed on its own."""
+    metric names.  One warm-up step, one timed step per form; then the other
+    SR form (the exact sample-space solve beside CG, or CG beside an exact
+    solve) on the same system, timed on its own."""
     from vqmc_inputs import init_theta, uniform_sz0
     wl = WORKLOADS[name]
     L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
@@ -162,7 +162,7 @@ def other_workload(V, torch, name, convs):
     spins = torch.from_numpy(uniform_sz0(L, B, seed=1)).to(dev)
     spins_np = spins.cpu().numpy()
     res = {"workload": "%s periodic J1-J2 (J2/J1=0.5), C=%d, n=%d, B=%d uniform Sz=0 configurations; "
-                       "E_loc (light cone) + O_k + SR (exact, %s)" % (name, C, n, B, SR_NAMES[wl["sr"]])}
+                       "E_loc (light cone) + O_k + SR (%s)" % (name, C, n, B, SR_NAMES[wl["sr"]])}
     base = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_FP32, V.ELOC_AUTO)
     P = V.num_params(base)
     O = torch.empty((B, P), dtype=torch.float32, device=dev)
@@ -185,7 +185,7 @@ def other_workload(V, torch, name, convs):
             ev[1].record()
             V.vqmc_log_derivs(base, th, spins, O=O, workspace=ws_o)
             ev[2].record()
-            V.vqmc_sr_solve(O, e, opts, delta=delta, workspace=ws_sr, want_info=False)
+            _, _, info = V.vqmc_sr_solve(O, e, opts, delta=delta, workspace=ws_sr)
             ev[3].record()
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
@@ -196,24 +196,31 @@ def other_workload(V, torch, name, convs):
                      "eloc": "lightcone" if lightcone else "dense",
                      "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
                      "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12}
-        if wl["sr"] == "dual":
-            # lower half of the B x B Gram matrix: B^2 P FLOPs (FP64 matrix cores)
-            res[conv]["gram_tflop"] = B * B * P / 1e12
+        if wl["sr"] == "cg":
+            res[conv].update({"cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
+                              "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9})
         del ws_e
-    # matrix-free CG on the last O, e (each iteration streams O twice)
+    # the other SR form on the last O, e
     del ws_sr
-    oc = sr_opts(V, "cg")
-    ws_c = torch.empty(max(V.sr_workspace(B, P, oc), 1), dtype=torch.uint8, device=dev)
+    other = "dual" if wl["sr"] == "cg" else "cg"
+    oo = sr_opts(V, other)
+    ws_c = torch.empty(max(V.sr_workspace(B, P, oo), 1), dtype=torch.uint8, device=dev)
     for it in range(2):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         torch.cuda.synchronize()
         ev[0].record()
-        _, _, info = V.vqmc_sr_solve(O, e, oc, delta=delta, workspace=ws_c)
+        _, _, oinfo = V.vqmc_sr_solve(O, e, oo, delta=delta, workspace=ws_c)
         ev[1].record()
         torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1])
-    res["sr_cg"] = {"sr_solve_ms": ms, "cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
-                    "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (ms / 1e3) / 1e9}
+    if other == "dual":
+        # lower half of the B x B Gram matrix: B^2 P FLOPs on the FP64 matrix cores
+        res["sr_dual"] = {"sr_solve_ms": ms, "gram_tflop": B * B * P / 1e12,
+                          "gram_tflops": B * B * P / (ms / 1e3) / 1e12}
+    else:
+        res["sr_cg"] = {"sr_solve_ms": ms, "cg_iterations": oinfo["iters"],
+                        "cg_rel_residual": oinfo["rel_residual"],
+                        "cg_hbm_gbs": oinfo["iters"] * 2 * B * P * 4 / (ms / 1e3) / 1e9}
     del ws_c
     return res
 
