@@ -4,8 +4,9 @@
 // input changes on two sites only, so after the l-th 3x3 convolution the
 // activations differ from those of s only within Chebyshev distance l of the
 // pair (its "light cone").  The kernel runs the dense forward pass of s once
-// per sample (FP32), keeps every pre-activation z_l(s) in a per-workgroup
-// scratch slice, and then for each s' propagates only the difference:
+// per sample (FP32), keeps e^{2 z_l(s)} of every pre-activation z_l(s) in a
+// per-workgroup scratch slice, and then for each s' propagates only the
+// difference:
 //   dz_l = W_l (*) dh_{l-1}           (matrix cores, rows = cone sites)
 //   dh_l = tanh(z_l + dz_l) - tanh(z_l) = tanh(dz_l) (1 - tanh(z_l) tanh(z_l + dz_l))
 // and log|W(s')| - log|W(s)| = sum over the last cone of dh_{n+1}.  The
@@ -72,21 +73,24 @@ __device__ __forceinline__ int bscan(int v, int *tmp, int *total) {
   return base + x - v;
 }
 
-// tanh(a + b) - tanh(a) with the relative accuracy of b.  With
-// E_a = e^{2a} and E_c = e^{2(a+b)}:
+// The dense pass stores E_a = e^{2a} of every pre-activation a, clamped to
+// a in [-40, 40] (e^80 < FLT_MAX; tanh is exactly +-1 in FP32 long before):
+// tanh(a) = 1 - 2 / (E_a + 1).
+__device__ __forceinline__ float exp2x(float a) { return __expf(2.f * fminf(fmaxf(a, -40.f), 40.f)); }
+
+// tanh(a + b) - tanh(a) from E_a = e^{2a}, with the relative accuracy of b.
+// With E_c = E_a e^{2b}:
 //   tanh(a + b) - tanh(a) = 2 (E_c - E_a) / ((E_c + 1)(E_a + 1)),
 // where E_c - E_a = E_a (e^{2b} - 1) is taken from the series of e^x - 1
 // (six terms) when |2b| < 0.25 (truncation below 5e-8 relative) and as the
 // plain difference otherwise (the two then differ by a factor e^{0.25} or
 // more, so the difference loses at most a factor 4.5 in relative accuracy).
-// Arguments are clamped to +-40 (e^80 < FLT_MAX; tanh is exactly +-1 in FP32
-// long before); a clamp only acts where both tanh values are saturated and
-// the result is 0 to FP32 precision either way.  Two exponentials and one
-// reciprocal.
-__device__ __forceinline__ float tanh_diff(float a, float b) {
-  const float ac = fminf(fmaxf(a, -40.f), 40.f), cc = fminf(fmaxf(a + b, -40.f), 40.f);
+// E_c is capped at 1e30: beyond it tanh(a + b) = 1 in FP32.  Where the
+// denominator overflows (E_a > 3e8 with E_c capped) the result is 0, within
+// 1e-8 of the exact 2 / (E_a + 1).  One exponential and one reciprocal.
+__device__ __forceinline__ float tanh_diff(float ea, float b) {
   const float x = 2.f * b;
-  const float ea = __expf(2.f * ac), ec = __expf(2.f * cc);
+  const float ec = fminf(ea * __expf(fminf(x, 88.f)), 1e30f);
   const float em1 =
       x * (1.f + x * (1.f / 2.f + x * (1.f / 6.f + x * (1.f / 24.f + x * (1.f / 120.f + x * (1.f / 720.f))))));
   // both candidates are formed and one is picked bitwise (no branch)
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
     }
     const double diag = bsum<NW>(dsum, s_red);
 
-    // ---- dense FP32 forward of s, keeping every pre-activation z_l(s)
+    // ---- dense FP32 forward of s, keeping e^{2 z_l(s)} of every pre-activation
     {
       const float *W0 = theta, *b0 = theta + 9 * C;
       for (int idx = tid; idx < N * C; idx += NW * 64) {
@@ -259,7 +263,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         float z = b0[co];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) z += W0[co * 9 + tap] * (float)s_sig[s_nbt[tap * MR + row]];
-        zsc[idx] = z;
+        zsc[idx] = exp2x(z);
         E32::store_act(s_act, row, co, tanh_f(z));
       }
       wait_copies();
@@ -284,7 +288,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
               const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + jj;
               if (row < N && co < C) {
                 const float z = acc[i][nt][jj] + bv;
-                zl[row * C + co] = z;
+                zl[row * C + co] = exp2x(z);
                 if (l < n_layers) E32::store_act(s_act, row, co, tanh_f(z));
               }
             }
@@ -296,7 +300,8 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         // log|W_CNN(s)| from the stored last-layer pre-activations
         const float *zn = zsc + (size_t)n_layers * N * C;
         double lp = 0.0;
-        for (int idx = tid; idx < N * C; idx += NW * 64) lp += (double)tanh_f(zn[idx]);
+        for (int idx = tid; idx < N * C; idx += NW * 64)
+          lp += (double)(1.f - 2.f * __builtin_amdgcn_rcpf(zn[idx] + 1.f));
         lp = bsum<NW>(lp, s_red);
         if (tid == 0) lp_out[b] = lp;
       }
@@ -353,7 +358,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
         // the lane's output sites (four rows r0..r0+3 of each of its tiles,
         // walking the box row-major; rows past the box reuse a valid site)
-        // and their pre-activations z_l(s), requested before the K loop so
+        // and the stored e^{2 z_l(s)} there, requested before the K loop so
         // that the matrix work covers the memory latency
         const float *zl = zsc + (size_t)l * N * C;
         int osite[TPW][4];
@@ -362,7 +367,8 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         for (int i = 0; i < TPW; ++i) {
           if (i < nti) {
             const int r0 = (wave + i * NW) * 16 + (lane >> 4) * 4;
-            int ry = r0 / bx.W, rx = r0 - ry * bx.W;
+            // r0 / W from a float reciprocal with half-row margin (r0 < 2^10)
+            int ry = (int)(((float)r0 + 0.5f) * __builtin_amdgcn_rcpf((float)bx.W)), rx = r0 - ry * bx.W;
             int y = bx.ys + ry, x = bx.xs + rx;
             y = y < 0 ? y + L : (y >= L ? y - L : y);
             x = x < 0 ? x + L : (x >= L ? x - L : x);
