@@ -212,6 +212,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
   __shared__ int16_t s_bonds[4 * MR];
   __shared__ double s_red[NW];
   __shared__ int s_ired[NW];
+  __shared__ double s_dl[16 * NW];  // per-wave parts of the last 16 log-ratios
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = L * L, NB = 4 * N;
   const int per_frag32 = E32::KS * NT * 64 * E32::FRAG;
@@ -309,8 +310,23 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
 
     // ---- every exchanged configuration, one at a time.  On entry to each
     // s' the fragments of its first layer are in (or on their way to) LDS.
-    double eacc = diag;
+    // Each wave leaves its part of the log-ratio in s_dl; thread 0 turns
+    // them into terms 16 at a time (in s' order, the waves' parts summed in
+    // wave order), so that no s' waits on a block-wide reduction.
+    double eacc = diag;  // thread 0's
     bool finite = true;
+    auto flush = [&](int q_end, int count) {
+      for (int qq = q_end - count; qq < q_end; ++qq) {
+        double dlog = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) dlog += s_dl[(qq & 15) * NW + w];
+        const int kind = s_bonds[qq] / N;
+        const double J = kind < 2 ? J1 : J2;
+        const double mu = (marshall && kind < 2) ? -1.0 : 1.0;
+        finite = finite && isfinite(dlog);
+        eacc += 0.5 * J * mu * exp(dlog);
+      }
+    };
     for (int q = 0; q < total; ++q) {
       int bi, bj, kind, y0, x0, ey, ex;
       pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
@@ -321,6 +337,8 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         for (int idx = tid; idx < K::ACT / 16; idx += NW * 64) p[idx] = uint4{0, 0, 0, 0};
       }
       __syncthreads();
+      // every wave has written its parts of s' q-16 .. q-1 (before the barrier)
+      if (tid == 0 && q > 0 && (q & 15) == 0) flush(q, 16);
       // lift: dz_1[x][c] = sum_tap W0[c][tap] ds[x + d(tap)] on the distance-1 box
       {
         Box bx;
@@ -421,18 +439,15 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         if (l < n_layers) wait_copies();
         __syncthreads();
       }
-      const double dlog = bsum<NW>(part, s_red);
-      const double J = kind < 2 ? J1 : J2;
-      const double mu = (marshall && kind < 2) ? -1.0 : 1.0;
-      const double term = 0.5 * J * mu * exp(dlog);
-      finite = finite && isfinite(dlog);
-      eacc += term;
+      part = wave_sum(part);
+      if (lane == 0) s_dl[(q & 15) * NW + wave] = part;
     }
     // the copy started by the last layer of the last s' must land before the
     // next sample overwrites the buffer
     wait_copies();
     __syncthreads();
     if (tid == 0) {
+      if (total > 0) flush(total, total - ((total - 1) & ~15));
       e_loc[b] = eacc;
       if (flags) flags[b] = ((!isfinite(eacc) || !finite) ? 1 : 0) | (sz != 0 ? 2 : 0) | (bad ? 4 : 0);
     }
