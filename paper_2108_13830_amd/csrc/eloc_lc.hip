@@ -516,7 +516,7 @@ int lc_grid_c(int N, int B) {
     case 0: return lc_grid<C, PREC, 4, 1>(B);
     case 1: return lc_grid<C, PREC, 4, 2>(B);
     case 2: return lc_grid<C, PREC, 8, 2>(B);
-    default: return lc_grid<C, PREC, 8, 5>(B);
+    default: return PREC == P_F32 ? lc_grid<C, PREC, 8, 5>(B) : lc_grid<C, PREC, 12, 3>(B);
   }
 }
 
@@ -531,6 +531,8 @@ size_t lc_ws(const vqmc_model *m, int B) {
 template <int C, int PREC, int NW, int TPW>
 vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
                       int32_t *flags, double *lp, char *ws, hipStream_t st) {
+  // the workgroup's LDS rows hold one configuration's sites
+  if (m->L * m->L > LC<C, PREC, NW, TPW>::MR) return VQMC_ERR_SHAPE;
   const int n = m->n_layers;
   char *f32 = ws;
   char *fp = ws + al256(n * frag_bytes_per_layer<C, P_F32>());
@@ -553,7 +555,11 @@ vqmc_status lc_launch_c(const vqmc_model *m, const float *theta, const int8_t *s
     case 0: return lc_launch<C, PREC, 4, 1>(m, theta, spins, B, e_loc, flags, lp, ws, st);
     case 1: return lc_launch<C, PREC, 4, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
     case 2: return lc_launch<C, PREC, 8, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
-    default: return lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, lp, ws, st);
+    // BF16 forms: 12 waves of 3 tiles (more waves to hide the cone's latencies);
+    // FP32: 8 waves of 5 tiles
+    default:
+      return PREC == P_F32 ? lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, lp, ws, st)
+                           : lc_launch<C, PREC, 12, 3>(m, theta, spins, B, e_loc, flags, lp, ws, st);
   }
 }
 
