@@ -150,14 +150,17 @@ vqmc_status vqmc_log_psi(const vqmc_model *m, const float *theta,
  * written to the workspace, evaluated by either method above, and combined;
  * bit 1 of chain_flags is set if any rotation's value is non-finite.
  * workspace: dev, at least vqmc_local_energy_workspace bytes (may be NULL
- * when that is 0). */
+ * for the dense evaluation without symmetry). */
 vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                               const int8_t *spins, int32_t B, double *e_loc,
                               int32_t *chain_flags, void *workspace,
                               size_t ws_bytes, hipStream_t stream);
 
-/* Workspace (device bytes) vqmc_local_energy needs for this model and B
- * (0 for the dense evaluation without symmetry). */
+/* Workspace (device bytes) vqmc_local_energy needs for this model and B.
+ * For the dense evaluation without symmetry it is the room for the C -> C
+ * layers' weights packed once per call (n layers x 5-36 KiB), and optional:
+ * with a NULL workspace (or a smaller one) the weights are staged from theta
+ * for every batch instead, with the same results, more slowly. */
 vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes);
 
 /* Workspace (device bytes) needed by vqmc_log_derivs for this model. */

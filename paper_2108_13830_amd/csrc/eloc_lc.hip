@@ -173,22 +173,6 @@ __device__ __forceinline__ void kloop_n(int n, const char *act, const char *frag
   }
 }
 
-typedef __attribute__((address_space(3))) void *lds_ptr_t;
-
-// Starts copying one layer's packed fragments (bytes, a multiple of 1 KiB)
-// into LDS with direct-to-LDS loads: no registers are involved and each wave
-// instruction moves 1 KiB.  The copy is complete once every thread has
-// passed wait_copies() and a barrier.
-template <int NTHR>
-__device__ __forceinline__ void stage_async(char *dst, const char *__restrict__ src, int bytes) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = wave; c < (bytes >> 10); c += NTHR / 64)
-    __builtin_amdgcn_global_load_lds(src + (size_t)c * 1024 + lane * 16, (lds_ptr_t)(dst + c * 1024), 16, 0, 0);
-}
-
-// Waits for this thread's outstanding memory operations (the direct-to-LDS
-// copies included).
-__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
 
 template <int C, int PREC, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restrict__ theta,
@@ -455,42 +439,6 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
   }
 }
 
-// Packs the C -> C layers' weights in the engine's per-lane fragment order
-// for precision PREC: [layer][KS][NT][64] fragments.
-template <int C, int PREC>
-__global__ void pack_lc_kernel(const float *__restrict__ theta, int n_layers, char *__restrict__ out) {
-  using E = Engine<C, PREC, 1, 1>;
-  constexpr int PER = E::KS * E::NT * 64;
-  const int total = n_layers * PER;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
-    const int l = t / PER + 1, idx = t - (l - 1) * PER;
-    const int s = idx / (E::NT * 64), r2 = idx - s * (E::NT * 64);
-    const int nt = r2 >> 6, ln = r2 & 63;
-    const int n = nt * 16 + (ln & 15);
-    const float *W = theta + layer_offset(C, l);
-    if constexpr (PREC == P_F32) {
-      reinterpret_cast<float *>(out)[t] = E::wsel(W, 4 * s + (ln >> 4), n);
-    } else {
-      const int k0 = 32 * s + 8 * (ln >> 4);
-      u16x8 hi, lo;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const float w = E::wsel(W, k0 + j, n);
-        hi[j] = bf16_rne(w);
-        lo[j] = bf16_rne(w - bf16_f32(hi[j]));
-      }
-      reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 0)] = hi;
-      if constexpr (PREC == P_X3) reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 1)] = lo;
-    }
-  }
-}
-
-template <int C, int PREC>
-constexpr size_t frag_bytes_per_layer() {
-  using E = Engine<C, PREC, 1, 1>;
-  return (size_t)E::KS * E::NT * 64 * E::FRAG;
-}
-
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 // Launch shapes by lattice size: (waves per workgroup, row tiles per wave),
@@ -539,8 +487,8 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
   float *z = reinterpret_cast<float *>(fp + al256(n * frag_bytes_per_layer<C, PREC>()));
   const int t32 = n * Engine<C, P_F32, 1, 1>::KS * Engine<C, P_F32, 1, 1>::NT * 64;
   const int tp = n * Engine<C, PREC, 1, 1>::KS * Engine<C, PREC, 1, 1>::NT * 64;
-  pack_lc_kernel<C, P_F32><<<(t32 + 255) / 256, 256, 0, st>>>(theta, n, f32);
-  if (PREC != P_F32) pack_lc_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
+  pack_layer_frags_kernel<C, P_F32><<<(t32 + 255) / 256, 256, 0, st>>>(theta, n, f32);
+  if (PREC != P_F32) pack_layer_frags_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
   else fp = f32;
   eloc_lc_kernel<C, PREC, NW, TPW><<<lc_grid<C, PREC, NW, TPW>(B), NW * 64, 0, st>>>(
       theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags, lp);

@@ -62,6 +62,23 @@ __device__ __forceinline__ f32x4 mma_bf16(u16x8 a, u16x8 b, f32x4 c) {
                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// Starts copying one layer's packed fragments (bytes, a multiple of 1 KiB)
+// into LDS with direct-to-LDS loads: no registers are involved and each wave
+// instruction moves 1 KiB.  The copy is complete once every thread has
+// passed wait_copies() and a barrier.
+template <int NTHR>
+__device__ __forceinline__ void stage_async(char *dst, const char *__restrict__ src, int bytes) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < (bytes >> 10); c += NTHR / 64)
+    __builtin_amdgcn_global_load_lds(src + (size_t)c * 1024 + lane * 16, (lds_ptr_t)(dst + c * 1024), 16, 0, 0);
+}
+
+// Waits for this thread's outstanding memory operations (the direct-to-LDS
+// copies included).
+__device__ __forceinline__ void wait_copies() { __builtin_amdgcn_s_waitcnt(0); }
+
 // tanh(x) = 1 - 2 / (exp(2x) + 1): one exponential and one hardware
 // reciprocal (1 ulp); absolute error ~2e-7 over the whole real line
 // (saturates to +-1).
@@ -500,12 +517,22 @@ struct Engine {
   // FP64).  smem_act / smem_frag are this engine's LDS regions; nbt is the
   // neighbour table built by build_nbt for at least G configurations.
   // Begins and ends with the block synchronised.
+  // packed (nullable): the C -> C layers' fragments in this order, packed
+  // once per call (pack_layer_frags_kernel); each layer then arrives by
+  // direct-to-LDS copies that run while the previous layer's outputs are
+  // written.  Without it the weights are staged from theta.
+  static constexpr int FRAG_LAYER = KS * NT * 64 * FRAG;
+  static constexpr bool DMA_OK = FRAG_LAYER % 1024 == 0;
   __device__ static __forceinline__ void forward(const float *__restrict__ theta, int n_layers, const int8_t *sp,
                                                  int G, int N, char *smem_act, char *smem_frag,
-                                                 const uint16_t *nbt, double *lp) {
+                                                 const uint16_t *nbt, double *lp,
+                                                 const char *__restrict__ packed = nullptr) {
     const int R = G * N;
-    stage_weights(theta + layer_offset(C, 1), smem_frag);
+    const bool dma = DMA_OK && packed != nullptr;
+    if (dma) stage_async<NTHR>(smem_frag, packed, FRAG_LAYER);
+    else stage_weights(theta + layer_offset(C, 1), smem_frag);
     lift_tab(theta, sp, nbt, R, smem_act);
+    if (dma) wait_copies();
     __syncthreads();
     for (int l = 1; l <= n_layers; ++l) {
       f32x4 acc[TPW][NT];
@@ -513,8 +540,14 @@ struct Engine {
       __syncthreads();
       const float *bias = theta + layer_offset(C, l) + 9 * C * C;
       if (l < n_layers) {
-        write_tiles(acc, bias, R, smem_act, nullptr);
-        stage_weights(theta + layer_offset(C, l + 1), smem_frag);
+        if (dma) {
+          stage_async<NTHR>(smem_frag, packed + (size_t)l * FRAG_LAYER, FRAG_LAYER);
+          write_tiles(acc, bias, R, smem_act, nullptr);
+          wait_copies();
+        } else {
+          write_tiles(acc, bias, R, smem_act, nullptr);
+          stage_weights(theta + layer_offset(C, l + 1), smem_frag);
+        }
       } else {
         head_vals(acc, bias, R, reinterpret_cast<float *>(smem_act));
       }
@@ -533,5 +566,43 @@ struct Engine {
     __syncthreads();
   }
 };
+
+
+
+// Packs the C -> C layers' weights in the engine's per-lane fragment order
+// for precision PREC: [layer][KS][NT][64] fragments.
+template <int C, int PREC>
+__global__ void pack_layer_frags_kernel(const float *__restrict__ theta, int n_layers, char *__restrict__ out) {
+  using E = Engine<C, PREC, 1, 1>;
+  constexpr int PER = E::KS * E::NT * 64;
+  const int total = n_layers * PER;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int l = t / PER + 1, idx = t - (l - 1) * PER;
+    const int s = idx / (E::NT * 64), r2 = idx - s * (E::NT * 64);
+    const int nt = r2 >> 6, ln = r2 & 63;
+    const int n = nt * 16 + (ln & 15);
+    const float *W = theta + layer_offset(C, l);
+    if constexpr (PREC == P_F32) {
+      reinterpret_cast<float *>(out)[t] = E::wsel(W, 4 * s + (ln >> 4), n);
+    } else {
+      const int k0 = 32 * s + 8 * (ln >> 4);
+      u16x8 hi, lo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float w = E::wsel(W, k0 + j, n);
+        hi[j] = bf16_rne(w);
+        lo[j] = bf16_rne(w - bf16_f32(hi[j]));
+      }
+      reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 0)] = hi;
+      if constexpr (PREC == P_X3) reinterpret_cast<u16x8 *>(out)[E::frag_piece(t, 1)] = lo;
+    }
+  }
+}
+
+template <int C, int PREC>
+constexpr size_t frag_bytes_per_layer() {
+  using E = Engine<C, PREC, 1, 1>;
+  return (size_t)E::KS * E::NT * 64 * E::FRAG;
+}
 
 }  // namespace vqmc

@@ -192,7 +192,8 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const fl
                                                        int marshall, int G,
                                                        double *__restrict__ e_loc,
                                                        int32_t *__restrict__ flags,
-                                                       double *__restrict__ lp_out) {
+                                                       double *__restrict__ lp_out,
+                                                       const char *__restrict__ packed) {
   using E = Engine<C, PREC, NW, TPW>;
   constexpr int MR = E::MAXROWS;
   __shared__ __align__(16) char s_act[E::ACT_BYTES];
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const fl
         s_sp[idx] = v;
       }
       __syncthreads();
-      E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp);
+      E::forward(theta, n_layers, s_sp, Gb, N, s_act, s_frag, s_nbt, s_lp, packed);
       if (q0 == 0) lp0 = s_lp[0];
       for (int g = tid; g < Gb; g += E::NTHR) {
         const int q = q0 + g;
@@ -483,6 +484,8 @@ struct FwdArgs {
   uint64_t seed, counter_base;
   int R;           // 1, or 4 for the rotation-symmetrised amplitude
   double *lp_out;  // local energy: log|W_CNN(s)| per sample (nullable)
+  char *ws;        // local energy: room for the packed weight fragments (nullable)
+  size_t ws_bytes;
   hipStream_t stream;
 };
 
@@ -524,8 +527,17 @@ static vqmc_status launch(Kind kind, const FwdArgs &a) {
       logpsi_kernel<C, PREC, I::NW, I::TPW, true><<<grid, I::NW * 64, 0, a.stream>>>(
           a.theta, a.spins_in, a.B, a.L, a.n_layers, a.marshall, G, a.out_d, a.out_sign);
   } else {
+    // the C -> C layers' fragments packed once for the whole call, when the
+    // caller provided the room
+    const char *packed = nullptr;
+    if (E::DMA_OK && a.ws && a.ws_bytes >= (size_t)a.n_layers * E::FRAG_LAYER) {
+      const int total = a.n_layers * E::KS * E::NT * 64;
+      pack_layer_frags_kernel<C, PREC><<<(total + 255) / 256, 256, 0, a.stream>>>(a.theta, a.n_layers, a.ws);
+      packed = a.ws;
+    }
     eloc_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
-        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i, a.lp_out);
+        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i, a.lp_out,
+        packed);
   }
   VQMC_LAUNCH_CHECK();
   return VQMC_OK;
@@ -587,9 +599,26 @@ static size_t sym_head_bytes(const vqmc_model *m, int B) {
   return al256(V * N) + 2 * al256(V * 8) + al256(V * 4);
 }
 
+// Dense evaluation: room for the packed fragments of the C -> C layers (the
+// call also runs without it, staging the weights from theta per batch).
+static size_t dense_ws_bytes(const vqmc_model *m) {
+  const int C = m->channels, prec = m->conv_prec;
+  size_t per = 0;
+  switch (C) {
+    case 4: per = Engine<4, P_F32, 1, 1>::FRAG_LAYER; break;
+    case 8: per = prec == P_F32 ? Engine<8, P_F32, 1, 1>::FRAG_LAYER
+                  : prec == P_BF16 ? Engine<8, P_BF16, 1, 1>::FRAG_LAYER : Engine<8, P_X3, 1, 1>::FRAG_LAYER; break;
+    case 16: per = prec == P_F32 ? Engine<16, P_F32, 1, 1>::FRAG_LAYER
+                   : prec == P_BF16 ? Engine<16, P_BF16, 1, 1>::FRAG_LAYER : Engine<16, P_X3, 1, 1>::FRAG_LAYER; break;
+    default: per = prec == P_F32 ? Engine<32, P_F32, 1, 1>::FRAG_LAYER
+                   : prec == P_BF16 ? Engine<32, P_BF16, 1, 1>::FRAG_LAYER : Engine<32, P_X3, 1, 1>::FRAG_LAYER; break;
+  }
+  return per % 1024 == 0 ? al256((size_t)m->n_layers * per) : 0;
+}
+
 static size_t eloc_ws_bytes(const vqmc_model *m, int B) {
-  if (!m->symmetry) return use_lightcone(m) ? eloc_lc_workspace(m, B) : 0;
-  return sym_head_bytes(m, B) + (use_lightcone(m) ? eloc_lc_workspace(m, 4 * B) : 0);
+  const size_t inner = use_lightcone(m) ? eloc_lc_workspace(m, m->symmetry ? 4 * B : B) : dense_ws_bytes(m);
+  return (m->symmetry ? sym_head_bytes(m, B) : 0) + inner;
 }
 
 extern "C" vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes) {
@@ -621,6 +650,8 @@ static vqmc_status eloc_plain(const vqmc_model *m, const float *theta, const int
   a.out_i = flags;
   a.R = 1;
   a.lp_out = lp;
+  a.ws = reinterpret_cast<char *>(ws);
+  a.ws_bytes = ws ? ws_bytes : 0;
   a.stream = stream;
   return dispatch(K_ELOC, m->channels, m->conv_prec, a);
 }

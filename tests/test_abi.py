@@ -69,8 +69,9 @@ def test_argument_errors_need_no_gpu():
                                  nul, 0, nul) == 4
     lc4 = V.Model(16, 4, 2, eloc=V.ELOC_LIGHTCONE).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(lc4), 64, ct.byref(n)) == 1
+    # dense: room for the packed weights of the 8 layers (36 KiB each), optional
     dense = V.Model(16, 32, 8, eloc=V.ELOC_DENSE).c()
-    assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 0
+    assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 8 * 36864
     # the symmetrised local energy needs a workspace for its 4B rotated copies
     sym = V.Model(10, 16, 6, eloc=V.ELOC_DENSE, symmetry=1).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(sym), 64, ct.byref(n)) == 0

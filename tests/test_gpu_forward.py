@@ -265,3 +265,24 @@ def test_sampler_distribution_4x4():
     assert chi2 < 3 * keep.sum() + 20, (hist, exp)
     e_s = host(V.vqmc_local_energy(gm, to_dev(th), sd))
     assert abs(e_s.mean() - (p * el).sum()) < 5 * e_s.std() / math.sqrt(chains)
+
+
+@pytest.mark.parametrize("L,C,n,prec", [(10, 16, 6, V.PREC_FP32), (10, 16, 6, V.PREC_BF16), (10, 16, 6, V.PREC_BF16X3),
+                                        (8, 8, 2, V.PREC_BF16), (12, 32, 3, V.PREC_BF16X3), (6, 4, 2, V.PREC_FP32)])
+def test_local_energy_packed_weights_equal_staged(L, C, n, prec):
+    """The dense evaluation with its workspace (weights packed once per call)
+    and without one (weights staged from theta per batch) feed the matrix
+    cores the same values: the energies agree bit for bit."""
+    import ctypes as ct
+    gm = V.Model(L, C, n, prec=prec, eloc=V.ELOC_DENSE)
+    th = to_dev(init_theta(C, n, seed=0))
+    s = to_dev(uniform_sz0(L, 37, seed=3))
+    announce("packed vs staged", L, C, n, prec)
+    a = V.vqmc_local_energy(gm, th, s)
+    b = torch.empty_like(a)
+    mc = gm.c()
+    rc = V.lib().vqmc_local_energy(ct.byref(mc), ct.c_void_p(th.data_ptr()), ct.c_void_p(s.data_ptr()), 37,
+                                   ct.c_void_p(b.data_ptr()), None, None, 0, V._stream())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
