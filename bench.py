@@ -173,7 +173,7 @@ def other_workload(V, torch, name, convs):
     delta = torch.empty(P, dtype=torch.float64, device=dev)
     for conv in convs:
         gm = base.with_prec(conv)
-        lightcone = V.local_energy_workspace(gm, 1) > 0
+        lightcone = V.local_energy_method(gm) == V.ELOC_LIGHTCONE
         nb = V.local_energy_workspace(gm, B)
         ws_e = torch.empty(nb, dtype=torch.uint8, device=dev) if nb else None
         for it in range(2):
@@ -270,7 +270,7 @@ def main():
     th = torch.from_numpy(th_np).to(dev)
     eloc_mode = {"auto": V.ELOC_AUTO, "dense": V.ELOC_DENSE, "lightcone": V.ELOC_LIGHTCONE}[args.eloc]
     gm = V.Model(L, C, n, 1.0, 0.5, 1, V.PREC_NAMES[args.conv], eloc_mode)
-    lightcone = V.local_energy_workspace(gm, 1) > 0
+    lightcone = V.local_energy_method(gm) == V.ELOC_LIGHTCONE
     P = V.num_params(gm)
 
     # ---- inputs (resident before the timed region)

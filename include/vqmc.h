@@ -156,6 +156,11 @@ vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                               int32_t *chain_flags, void *workspace,
                               size_t ws_bytes, hipStream_t stream);
 
+/* The method vqmc_local_energy uses for this model (*method: VQMC_ELOC_DENSE
+ * or VQMC_ELOC_LIGHTCONE, AUTO resolved); VQMC_ERR_ARG when the model asks
+ * for the light cone and the light cone does not support it. */
+vqmc_status vqmc_local_energy_method(const vqmc_model *m, int32_t *method);
+
 /* Workspace (device bytes) vqmc_local_energy needs for this model and B.
  * For the dense evaluation without symmetry it is the room for the C -> C
  * layers' weights packed once per call (n layers x 5-36 KiB), and optional:

@@ -621,6 +621,13 @@ static size_t eloc_ws_bytes(const vqmc_model *m, int B) {
   return (m->symmetry ? sym_head_bytes(m, B) : 0) + inner;
 }
 
+extern "C" vqmc_status vqmc_local_energy_method(const vqmc_model *m, int32_t *method) {
+  if (!model_valid(m) || !method) return VQMC_ERR_ARG;
+  if (m->eloc_mode == VQMC_ELOC_LIGHTCONE && !eloc_lc_supported(m)) return VQMC_ERR_ARG;
+  *method = use_lightcone(m) ? VQMC_ELOC_LIGHTCONE : VQMC_ELOC_DENSE;
+  return VQMC_OK;
+}
+
 extern "C" vqmc_status vqmc_local_energy_workspace(const vqmc_model *m, int32_t B, size_t *bytes) {
   if (!model_valid(m) || !bytes) return VQMC_ERR_ARG;
   if (B < 0 || (m->symmetry && B > INT32_MAX / 4)) return VQMC_ERR_SHAPE;

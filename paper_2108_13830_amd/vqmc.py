@@ -111,6 +111,7 @@ SIGNATURES = [
     ("vqmc_log_psi", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP]),
     ("vqmc_local_energy", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP,
                                      ct.c_size_t, _VP]),
+    ("vqmc_local_energy_method", ct.c_int, [ct.POINTER(_Model), ct.POINTER(ct.c_int32)]),
     ("vqmc_local_energy_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32,
                                                ct.POINTER(ct.c_size_t)]),
     ("vqmc_log_derivs_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32,
@@ -197,6 +198,14 @@ def vqmc_log_psi(m: Model, theta, spins, out=None, sign=None):
     _check("vqmc_log_psi", lib().vqmc_log_psi(ct.byref(mc), _ptr(theta), _ptr(spins), B,
                                               _ptr(out), _ptr(sign), _stream()))
     return out
+
+
+def local_energy_method(m: Model) -> int:
+    """ELOC_DENSE or ELOC_LIGHTCONE: the method the library uses for m."""
+    mc = m.c()
+    r = ct.c_int32(0)
+    _check("vqmc_local_energy_method", lib().vqmc_local_energy_method(ct.byref(mc), ct.byref(r)))
+    return r.value
 
 
 def local_energy_workspace(m: Model, B: int) -> int:

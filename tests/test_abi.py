@@ -23,7 +23,7 @@ def declared():
 
 def test_every_declared_symbol_is_exported():
     names = declared()
-    assert len(names) == 12
+    assert len(names) == 13
     lib = ct.CDLL(V.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -69,6 +69,14 @@ def test_argument_errors_need_no_gpu():
                                  nul, 0, nul) == 4
     lc4 = V.Model(16, 4, 2, eloc=V.ELOC_LIGHTCONE).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(lc4), 64, ct.byref(n)) == 1
+    # the method a model resolves to
+    meth = ct.c_int32(-1)
+    assert lib.vqmc_local_energy_method(ct.byref(lc), ct.byref(meth)) == 0 and meth.value == V.ELOC_LIGHTCONE
+    auto24 = V.Model(24, 32, 8).c()
+    assert lib.vqmc_local_energy_method(ct.byref(auto24), ct.byref(meth)) == 0 and meth.value == V.ELOC_LIGHTCONE
+    auto10 = V.Model(10, 16, 6).c()
+    assert lib.vqmc_local_energy_method(ct.byref(auto10), ct.byref(meth)) == 0 and meth.value == V.ELOC_DENSE
+    assert lib.vqmc_local_energy_method(ct.byref(lc4), ct.byref(meth)) == 1
     # dense: room for the packed weights of the 8 layers (36 KiB each), optional
     dense = V.Model(16, 32, 8, eloc=V.ELOC_DENSE).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 8 * 36864
