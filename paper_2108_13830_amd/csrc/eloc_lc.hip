@@ -148,31 +148,192 @@ struct Box {
   }
 };
 
+// LDS plan of the kernel.  One region serves two phases in turn:
+//   dense pass of s:  FP32 activations [MR][C+1] | one layer's FP32 fragments
+//                     | neighbour table
+//   difference pass:  the fragments of two layers (the current one and the
+//                     next, copied while the current one runs) | two
+//                     difference buffers indexed by the row of the cone box
+//                     (odd boxes in one, even boxes in the other), each with
+//                     one extra row that stays zero.
 template <int C, int PREC, int NW, int TPW>
 struct LC {
   using E32 = Engine<C, P_F32, NW, TPW>;
   using EP = Engine<C, PREC, NW, TPW>;
   static constexpr int NT = E32::NT;
-  static constexpr int ACT = E32::ACT_BYTES > EP::ACT_BYTES ? E32::ACT_BYTES : EP::ACT_BYTES;
   static constexpr int MR = E32::MAXROWS;
-  static constexpr int FRAG = E32::FRAG_BYTES > EP::FRAG_BYTES ? E32::FRAG_BYTES : EP::FRAG_BYTES;
+  static constexpr int FRAG32 = E32::FRAG_BYTES;
+  static constexpr int FRAGP = EP::FRAG_BYTES;
+  static constexpr int BASE = E32::ACT_BYTES + FRAG32 + E32::NBT_ELEMS * 2;
+  // bytes per difference row: FP32 rows of C + 1 floats, or BF16 planes
+  static constexpr int ROWB = PREC == P_F32 ? 4 * (C + 1) : (PREC == P_X3 ? 4 * C : 2 * C);
+  static constexpr int SLOTS = 32;  // log-ratio parts in flight (two groups of 16)
+  static constexpr int FIXED = MR + 8 * MR + 8 * SLOTS * NW + 8 * NW + 4 * NW;
+  static constexpr int LIMIT = 160 * 1024 - 512;
+  static constexpr int ROWS_FIT = (LIMIT - FIXED - 2 * FRAGP) / ROWB;
+  // rows of both difference buffers together (zero rows included)
+  static constexpr int ROWS = ROWS_FIT < 2 * MR + 2 ? ROWS_FIT : 2 * MR + 2;
+  static constexpr int SPASS = 2 * FRAGP + ROWS * ROWB;
+  static constexpr int REGION = ((BASE > SPASS ? BASE : SPASS) + 15) / 16 * 16;
+  static_assert(REGION + FIXED <= 160 * 1024, "LDS plan exceeds the workgroup's 160 KiB");
+  static_assert(FRAGP % 1024 == 0 && FRAG32 % 1024 == 0, "fragment blocks are copied in 1 KiB pieces");
 };
 
-// The engine's K loop over the first n tile slots only (n wave-uniform,
-// 0 <= n <= TPW), dispatched to a compile-time trip count.  rows[i] is the
-// lattice site of the lane's output row in tile slot i.
-template <class EP, int TPW, int K = 1>
-__device__ __forceinline__ void kloop_n(int n, const char *act, const char *frag, const uint16_t *nbt,
-                                        const int (&rows)[TPW], f32x4 (&acc)[TPW][EP::NT]) {
-  if constexpr (K <= TPW) {
-    if (n <= K) {
-      EP::template kloop_rows<K>(act, frag, nbt, rows, acc);
-      return;
+// Rows of the largest cone box of distance l (the exchanged pair spans at
+// most 2x2 sites; clipped to the torus).
+__host__ __device__ inline int box_rows_max(int l, int L) {
+  const int e = 2 + 2 * l < L ? 2 + 2 * l : L;
+  return e * e;
+}
+
+// Capacities (rows, zero row excluded) of the odd-box and even-box buffers
+// for n layers: the stored boxes are those of distance 1 .. n.
+__host__ __device__ inline void lc_caps(int n, int L, int &cap_odd, int &cap_even) {
+  cap_odd = box_rows_max((n & 1) ? n : n - 1, L);
+  cap_even = n >= 2 ? box_rows_max((n & 1) ? n - 1 : n, L) : 0;
+}
+
+// Difference buffer of cap + 1 rows (row cap stays zero): FP32 rows of C + 1
+// floats, or the BF16 hi plane of (cap + 1) * C values followed (split form)
+// by the lo plane; rows are swizzled as in the engine.
+template <int C, int PREC>
+__device__ __forceinline__ void dstore4(char *buf, int cap, int row, int co0, const float (&h)[4]) {
+  using E = Engine<C, PREC, 1, 1>;
+  if constexpr (PREC == P_F32) {
+    float *p = reinterpret_cast<float *>(buf) + row * (C + 1) + co0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) p[j] = h[j];
+  } else {
+    uint16_t *hi = reinterpret_cast<uint16_t *>(buf);
+    const int pi = E::phys(row, co0);
+    uint16_t b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = bf16_rne(h[j]);
+    *reinterpret_cast<uint2 *>(hi + pi) =
+        uint2{(uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16)};
+    if constexpr (PREC == P_X3) {
+      uint16_t c[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[j] = bf16_rne(h[j] - bf16_f32(b[j]));
+      *reinterpret_cast<uint2 *>(hi + (cap + 1) * C + pi) =
+          uint2{(uint32_t)c[0] | ((uint32_t)c[1] << 16), (uint32_t)c[2] | ((uint32_t)c[3] << 16)};
     }
-    kloop_n<EP, TPW, K + 1>(n, act, frag, nbt, rows, acc);
   }
 }
 
+template <int C, int PREC>
+__device__ __forceinline__ int dbuf_bytes(int cap) {
+  return PREC == P_F32 ? (cap + 1) * (C + 1) * 4 : (cap + 1) * C * (PREC == P_X3 ? 4 : 2);
+}
+
+__device__ __forceinline__ int sel3(const int (&v)[3], int d) { return d == 0 ? v[0] : (d == 1 ? v[1] : v[2]); }
+
+// K loop of one C -> C layer of the difference pass over the first NTILE
+// tile slots, in transposed tiles (acc[i][nt][j]: channel 16 nt + 4 (lane/16)
+// + j of the lane's output row).  The input of the lane's row at tap
+// (dy, dx) is row ro[i][dy] + cf[i][dx] of the input box, or the zero row
+// cap when that sum is negative (outside the box).
+template <int C, int PREC, int TPW, int NTILE>
+__device__ __forceinline__ void kloop_box(const char *in, int cap, const char *frag, const int (&ro)[TPW][3],
+                                          const int (&cf)[TPW][3], f32x4 (&acc)[TPW][(C + 15) / 16]) {
+  using E = Engine<C, PREC, 1, 1>;
+  constexpr int NT = E::NT;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[i][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (PREC == P_F32) {
+    const float *actf = reinterpret_cast<const float *>(in) + (lane >> 4);
+    const float *fragf = reinterpret_cast<const float *>(frag) + lane;
+    constexpr int SPT = C / 4;
+#pragma unroll 3
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      int nb[NTILE];
+#pragma unroll
+      for (int i = 0; i < NTILE; ++i) {
+        const int g = sel3(ro[i], dy) + sel3(cf[i], dx);
+        nb[i] = (g < 0 ? cap : g) * (C + 1);
+      }
+#pragma unroll
+      for (int c4 = 0; c4 < SPT; ++c4) {
+        const int s = tap * SPT + c4;
+        float b[NT], a[NTILE];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b[nt] = fragf[(s * NT + nt) * 64];
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i) a[i] = actf[nb[i] + 4 * c4];
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(b[nt], a[i], acc[i][nt]);
+      }
+    }
+  } else {
+    const uint16_t *hi = reinterpret_cast<const uint16_t *>(in);
+    const uint16_t *lo = hi + (cap + 1) * C;
+#pragma unroll
+    for (int s = 0; s < E::KS; ++s) {
+      u16x8 bh[NT], bl[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const u16x8 *f = reinterpret_cast<const u16x8 *>(frag) + E::frag_piece((s * NT + nt) * 64 + lane, 0);
+        bh[nt] = f[0];
+        if constexpr (PREC == P_X3) bl[nt] = f[64];
+      }
+      const int k0 = 32 * s + 8 * (lane >> 4);
+      const bool kv = k0 < 9 * C;
+      // with C >= 32 a K-step lies within one tap (known at compile time);
+      // lanes whose K slice lies past 9C read a valid row and multiply zero
+      // weights
+      const int tap = C >= 32 ? (32 * s) / C : (kv ? k0 / C : 0);
+      const int ci0 = kv ? k0 - tap * C : 0;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      u16x8 ah[NTILE], al[NTILE];
+#pragma unroll
+      for (int i = 0; i < NTILE; ++i) {
+        const int g = sel3(ro[i], dy) + sel3(cf[i], dx);
+        const int p = E::phys(g < 0 ? cap : g, ci0);
+        ah[i] = *reinterpret_cast<const u16x8 *>(hi + p);
+        if constexpr (PREC == P_X3) al[i] = *reinterpret_cast<const u16x8 *>(lo + p);
+      }
+#pragma unroll
+      for (int i = 0; i < NTILE; ++i)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[i][nt] = mma_bf16(bh[nt], ah[i], acc[i][nt]);
+          if constexpr (PREC == P_X3) {
+            acc[i][nt] = mma_bf16(bl[nt], ah[i], acc[i][nt]);
+            acc[i][nt] = mma_bf16(bh[nt], al[i], acc[i][nt]);
+          }
+        }
+    }
+  }
+}
+
+template <int V>
+struct IntC {
+  static constexpr int value = V;
+};
+
+// Calls f(IntC<n>) for the wave-uniform n in [0, TPW].
+template <int TPW, int K = 0, class F>
+__device__ __forceinline__ void with_tiles(int n, F &f) {
+  if constexpr (K <= TPW) {
+    if (n == K) {
+      f(IntC<K>{});
+      return;
+    }
+    with_tiles<TPW, K + 1>(n, f);
+  }
+}
+
+// a - b reduced to [0, L) for a - b in (-L, 2L)
+__device__ __forceinline__ int mod_once(int v, int L) {
+  v += v < 0 ? L : 0;
+  return v >= L ? v - L : v;
+}
 
 template <int C, int PREC, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restrict__ theta,
@@ -180,38 +341,44 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
                                                           const char *__restrict__ fragp,
                                                           const int8_t *__restrict__ spins, int B, int L,
                                                           int n_layers, double J1, double J2, int marshall,
+                                                          int cap_odd, int cap_even,
                                                           float *__restrict__ zscratch,
                                                           double *__restrict__ e_loc,
                                                           int32_t *__restrict__ flags,
                                                           double *__restrict__ lp_out) {
   using K = LC<C, PREC, NW, TPW>;
   using E32 = typename K::E32;
-  using EP = typename K::EP;
   constexpr int NT = K::NT;
   constexpr int MR = K::MR;
-  __shared__ __align__(16) char s_act[K::ACT];
-  __shared__ __align__(16) char s_frag[K::FRAG];
-  __shared__ uint16_t s_nbt[E32::NBT_ELEMS];
+  constexpr int NTHR = NW * 64;
+  __shared__ __align__(16) char s_region[K::REGION];
   __shared__ int8_t s_sig[MR];
   __shared__ int16_t s_bonds[4 * MR];
+  __shared__ double s_dl[K::SLOTS * NW];  // per-wave parts of the log-ratios in flight
   __shared__ double s_red[NW];
   __shared__ int s_ired[NW];
-  __shared__ double s_dl[16 * NW];  // per-wave parts of the last 16 log-ratios
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // dense pass of s
+  char *s_act = s_region;
+  char *s_frag = s_region + E32::ACT_BYTES;
+  uint16_t *s_nbt = reinterpret_cast<uint16_t *>(s_region + E32::ACT_BYTES + K::FRAG32);
+  // difference pass
+  // fragment buffer i (0, 1) of the difference pass: s_region + i * K::FRAGP
+  char *s_dodd = s_region + 2 * K::FRAGP;
+  char *s_deven = s_dodd + dbuf_bytes<C, PREC>(cap_odd);
+  // the wave index is uniform across the wave: kept in a scalar register,
+  // so that per-wave tile counts branch on scalars
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int N = L * L, NB = 4 * N;
-  const int per_frag32 = E32::KS * NT * 64 * E32::FRAG;
-  const int per_fragp = EP::KS * NT * 64 * EP::FRAG;
-  static_assert((E32::KS * NT * 64 * E32::FRAG) % 1024 == 0 && (EP::KS * NT * 64 * EP::FRAG) % 1024 == 0,
-                "fragment blocks are copied in 1 KiB pieces");
   float *zsc = zscratch + (size_t)blockIdx.x * (n_layers + 1) * N * C;
-  // neighbour table of the single configuration: nbt[tap][site]
-  E32::build_nbt(s_nbt, 1, L, N);
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     const int8_t *s = spins + (size_t)b * N;
     // the first FP32 layer's fragments arrive while the bonds are scanned
-    stage_async<NW * 64>(s_frag, frag32, per_frag32);
+    stage_async<NTHR>(s_frag, frag32, K::FRAG32);
+    // neighbour table of the single configuration, nbt[tap][site] (the
+    // difference pass reuses its room)
+    E32::build_nbt(s_nbt, 1, L, N);
     int sz = 0, bad = 0;
-    for (int i = tid; i < N; i += NW * 64) {
+    for (int i = tid; i < N; i += NTHR) {
       const int8_t v = s[i];
       s_sig[i] = v;
       sz += v;
@@ -220,7 +387,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
     sz = bisum<NW>(sz, s_ired);
     bad = bisum<NW>(bad, s_ired);
     // ---- bond scan (diagonal term, ordered antiparallel list)
-    const int chunk = (NB + NW * 64 - 1) / (NW * 64);
+    const int chunk = (NB + NTHR - 1) / NTHR;
     const int k0 = tid * chunk, k1 = min(k0 + chunk, NB);
     double dsum = 0.0;
     int cnt = 0;
@@ -243,7 +410,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
     // ---- dense FP32 forward of s, keeping e^{2 z_l(s)} of every pre-activation
     {
       const float *W0 = theta, *b0 = theta + 9 * C;
-      for (int idx = tid; idx < N * C; idx += NW * 64) {
+      for (int idx = tid; idx < N * C; idx += NTHR) {
         const int row = idx / C, co = idx - row * C;
         float z = b0[co];
 #pragma unroll
@@ -254,29 +421,39 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
       wait_copies();
       __syncthreads();
       for (int l = 1; l <= n_layers; ++l) {
+        // transposed tiles: lane holds channels co0..co0+3 of one row
         f32x4 acc[TPW][NT];
-        E32::kloop_tab(s_act, s_frag, s_nbt, acc);
+        E32::template kloop_tab<true>(s_act, s_frag, s_nbt, acc);
         __syncthreads();
-        // next: the following FP32 layer, or the first layer of the s' pass
-        if (l < n_layers) stage_async<NW * 64>(s_frag, frag32 + (size_t)l * per_frag32, per_frag32);
-        else stage_async<NW * 64>(s_frag, fragp, per_fragp);
+        // next: the following FP32 layer, or the first layer of the
+        // difference pass (into the first fragment buffer, which overlaps
+        // room of this pass that is no longer read)
+        if (l < n_layers) stage_async<NTHR>(s_frag, frag32 + (size_t)l * K::FRAG32, K::FRAG32);
+        else stage_async<NTHR>(s_region, fragp, K::FRAGP);
         const float *bias = theta + layer_offset(C, l) + 9 * C * C;
         float *zl = zsc + (size_t)l * N * C;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const int co = nt * 16 + (lane & 15);
-          const float bv = co < C ? bias[co] : 0.f;
+          const int co0 = nt * 16 + 4 * (lane >> 4);
+          float bv[4];
 #pragma unroll
-          for (int i = 0; i < TPW; ++i)
+          for (int jj = 0; jj < 4; ++jj) bv[jj] = bias[co0 + jj];
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + jj;
-              if (row < N && co < C) {
-                const float z = acc[i][nt][jj] + bv;
-                zl[row * C + co] = exp2x(z);
-                if (l < n_layers) E32::store_act(s_act, row, co, tanh_f(z));
+          for (int i = 0; i < TPW; ++i) {
+            const int row = (wave + i * NW) * 16 + (lane & 15);
+            if (row < N) {
+              f32x4 e;
+              float h[4];
+#pragma unroll
+              for (int jj = 0; jj < 4; ++jj) {
+                const float z = acc[i][nt][jj] + bv[jj];
+                e[jj] = exp2x(z);
+                h[jj] = tanh_f(z);
               }
+              *reinterpret_cast<f32x4 *>(zl + row * C + co0) = e;
+              if (l < n_layers) E32::store_act4(s_act, row, co0, h);
             }
+          }
         }
         wait_copies();
         __syncthreads();
@@ -285,25 +462,73 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         // log|W_CNN(s)| from the stored last-layer pre-activations
         const float *zn = zsc + (size_t)n_layers * N * C;
         double lp = 0.0;
-        for (int idx = tid; idx < N * C; idx += NW * 64)
+        for (int idx = tid; idx < N * C; idx += NTHR)
           lp += (double)(1.f - 2.f * __builtin_amdgcn_rcpf(zn[idx] + 1.f));
         lp = bsum<NW>(lp, s_red);
         if (tid == 0) lp_out[b] = lp;
       }
     }
 
-    // ---- every exchanged configuration, one at a time.  On entry to each
-    // s' the fragments of its first layer are in (or on their way to) LDS.
-    // Each wave leaves its part of the log-ratio in s_dl; thread 0 turns
-    // them into terms 16 at a time (in s' order, the waves' parts summed in
-    // wave order), so that no s' waits on a block-wide reduction.
+    // ---- every exchanged configuration.  Layer l reads the differences on
+    // the box of distance l (odd l: s_dodd, even l: s_deven) and writes those
+    // on the box of distance l + 1 into the other buffer, so one barrier per
+    // layer suffices; the fragments of the layer after the current one are
+    // copied into the other fragment buffer meanwhile.  Each wave leaves its
+    // part of the log-ratio in s_dl; thread 0 turns them into terms 16 at a
+    // time (in s' order, the waves' parts summed in wave order).
+    // zero rows of both buffers (the dense pass used their room)
+    {
+      const int wb = PREC == P_F32 ? (C + 1) : (PREC == P_X3 ? C : C / 2);  // 32-bit words per zero row
+      for (int idx = tid; idx < 2 * wb; idx += NTHR) {
+        const int bsel = idx / wb, w = idx - bsel * wb;
+        char *buf = bsel ? s_deven : s_dodd;
+        const int cap = bsel ? cap_even : cap_odd;
+        uint32_t *p;
+        if constexpr (PREC == P_F32) {
+          p = reinterpret_cast<uint32_t *>(buf) + cap * (C + 1) + w;
+        } else {
+          // hi plane row cap, then (split form) lo plane row cap
+          const int half = C / 2;  // words per plane row
+          p = w < half ? reinterpret_cast<uint32_t *>(buf) + cap * half + w
+                       : reinterpret_cast<uint32_t *>(buf) + (cap + 1) * half + cap * half + (w - half);
+        }
+        *p = 0u;
+      }
+    }
+    // lift of s' q into the odd buffer: dz_1 = sum_tap W0[c][tap] ds(x + d(tap))
+    // on the box of distance 1, four channels per thread
+    auto lift = [&](int q) {
+      int bi, bj, kind, y0, x0, ey, ex;
+      pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
+      const float dsi = (float)(s_sig[bj] - s_sig[bi]);  // change of spin at bi (at bj: -dsi)
+      Box bx;
+      bx.set(y0, x0, ey, ex, 1, L);
+      const int R = bx.H * bx.W;
+      for (int idx = tid; idx < R * (C / 4); idx += NTHR) {
+        const int r = idx / (C / 4), co0 = 4 * (idx - r * (C / 4));
+        const int site = bx.site(r, L), y = site / L, x = site - y * L;
+        float dz[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+          const int nb = wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L);
+          const float d = nb == bi ? dsi : (nb == bj ? -dsi : 0.f);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dz[j] += theta[(co0 + j) * 9 + tap] * d;
+        }
+        const f32x4 e = *reinterpret_cast<const f32x4 *>(zsc + site * C + co0);
+        float dh[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dh[j] = tanh_diff(e[j], dz[j]);
+        dstore4<C, PREC>(s_dodd, cap_odd, r, co0, dh);
+      }
+    };
     double eacc = diag;  // thread 0's
     bool finite = true;
     auto flush = [&](int q_end, int count) {
       for (int qq = q_end - count; qq < q_end; ++qq) {
         double dlog = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) dlog += s_dl[(qq & 15) * NW + w];
+        for (int w = 0; w < NW; ++w) dlog += s_dl[(qq & (K::SLOTS - 1)) * NW + w];
         const int kind = s_bonds[qq] / N;
         const double J = kind < 2 ? J1 : J2;
         const double mu = (marshall && kind < 2) ? -1.0 : 1.0;
@@ -311,125 +536,115 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         eacc += 0.5 * J * mu * exp(dlog);
       }
     };
+    if (total > 0) lift(0);
+    __syncthreads();
+    int t = 0;  // layers run so far: the current layer's fragments are in buffer t & 1
     for (int q = 0; q < total; ++q) {
       int bi, bj, kind, y0, x0, ey, ex;
       pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
-      const float dsi = (float)(s_sig[bj] - s_sig[bi]);  // change of spin at bi (at bj: -dsi)
-      // clear the difference buffer
-      {
-        uint4 *p = reinterpret_cast<uint4 *>(s_act);
-        for (int idx = tid; idx < K::ACT / 16; idx += NW * 64) p[idx] = uint4{0, 0, 0, 0};
-      }
-      __syncthreads();
-      // every wave has written its parts of s' q-16 .. q-1 (before the barrier)
+      // every wave has written its parts of s' q-16 .. q-1 (before a barrier);
+      // the slots written meanwhile (s' q onwards) are the other 16
       if (tid == 0 && q > 0 && (q & 15) == 0) flush(q, 16);
-      // lift: dz_1[x][c] = sum_tap W0[c][tap] ds[x + d(tap)] on the distance-1 box
-      {
-        Box bx;
-        bx.set(y0, x0, ey, ex, 1, L);
-        const int R = bx.H * bx.W;
-        for (int idx = tid; idx < R * C; idx += NW * 64) {
-          const int r = idx / C, co = idx - r * C;
-          const int site = bx.site(r, L);
-          float dz = 0.f;
-#pragma unroll
-          for (int tap = 0; tap < 9; ++tap) {
-            const int nb = s_nbt[tap * MR + site];
-            const float w = theta[co * 9 + tap];
-            dz += nb == bi ? w * dsi : (nb == bj ? -w * dsi : 0.f);
-          }
-          EP::store_act(s_act, site, co, tanh_diff(zsc[site * C + co], dz));
-        }
-      }
-      wait_copies();
-      __syncthreads();
       double part = 0.0;
       for (int l = 1; l <= n_layers; ++l) {
-        Box bx;
-        bx.set(y0, x0, ey, ex, l + 1, L);
-        const int R = bx.H * bx.W;
-        int rows[TPW];
-#pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-          int r = (wave + i * NW) * 16 + (lane & 15);
-          r = r < R ? r : R - 1;
-          rows[i] = bx.site(r, L);
-        }
-        // tiles of this wave in the current box (wave-uniform)
+        const char *din = (l & 1) ? s_dodd : s_deven;
+        const int cap_in = (l & 1) ? cap_odd : cap_even;
+        char *dout = (l & 1) ? s_deven : s_dodd;
+        const int cap_out = (l & 1) ? cap_even : cap_odd;
+        Box bo, bn;
+        bn.set(y0, x0, ey, ex, l, L);      // input box
+        bo.set(y0, x0, ey, ex, l + 1, L);  // output box
+        const int R = bo.H * bo.W;
+        // tiles of this wave in the output box (wave-uniform)
         const int Ttot = (R + 15) / 16;
         const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
-        // the lane's output sites (four rows r0..r0+3 of each of its tiles,
-        // walking the box row-major; rows past the box reuse a valid site)
-        // and the stored e^{2 z_l(s)} there, requested before the K loop so
-        // that the matrix work covers the memory latency
+        // the lane's output row in tile slot i (rows past the box repeat the
+        // last one and are not stored): its lattice site, and the rows of
+        // the input box that its 3x3 neighbourhood reads
         const float *zl = zsc + (size_t)l * N * C;
-        int osite[TPW][4];
-        float za[TPW][4][NT];
+        const char *fcur = s_region + (t & 1) * K::FRAGP;
+        // the next layer's fragments (after the last layer: the first one's,
+        // for the next s') go into the other buffer, read last by the
+        // previous layer
+        const bool copy_next = l < n_layers || q + 1 < total;
+        char *fnext = s_region + ((t + 1) & 1) * K::FRAGP;
+        const char *fsrc = fragp + (size_t)(l < n_layers ? l : 0) * K::FRAGP;
+        // One compile-time body per tile count of this wave: the loaded
+        // exponentials are used only inside it (a register copy at a branch
+        // merge would wait for them, and for the fragment copy issued after
+        // them, before the K loop).
+        auto body = [&](auto ntile) {
+          constexpr int NTILE = decltype(ntile)::value;
+          // the lane's output row in tile slot i (rows past the box repeat
+          // the last one and are not stored): its lattice site, and the rows
+          // of the input box that its 3x3 neighbourhood reads
+          int site[TPW], ro[TPW][3], cf[TPW][3];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-          if (i < nti) {
-            const int r0 = (wave + i * NW) * 16 + (lane >> 4) * 4;
-            // r0 / W from a float reciprocal with half-row margin (r0 < 2^10)
-            int ry = (int)(((float)r0 + 0.5f) * __builtin_amdgcn_rcpf((float)bx.W)), rx = r0 - ry * bx.W;
-            int y = bx.ys + ry, x = bx.xs + rx;
-            y = y < 0 ? y + L : (y >= L ? y - L : y);
-            x = x < 0 ? x + L : (x >= L ? x - L : x);
+          for (int i = 0; i < NTILE; ++i) {
+            int r = (wave + i * NW) * 16 + (lane & 15);
+            r = r < R ? r : R - 1;
+            const int ry = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)bo.W)), rx = r - ry * bo.W;
+            const int y = mod_once(bo.ys + ry, L), x = mod_once(bo.xs + rx, L);
+            site[i] = y * L + x;
+            const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              osite[i][jj] = y * L + x;
-              ++rx;
-              x = x + 1 == L ? 0 : x + 1;
-              if (rx == bx.W) {
-                rx = 0;
-                x = bx.xs < 0 ? bx.xs + L : bx.xs;
-                y = y + 1 == L ? 0 : y + 1;
-              }
+            for (int d = 0; d < 3; ++d) {
+              int vy = ay + d - 1, vx = ax + d - 1;
+              vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
+              vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
+              ro[i][d] = vy < bn.H ? vy * bn.W : -(1 << 20);
+              cf[i][d] = vx < bn.W ? vx : -(1 << 20);
             }
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
-#pragma unroll
-              for (int nt = 0; nt < NT; ++nt) {
-                const int co = nt * 16 + (lane & 15);
-                za[i][jj][nt] = zl[osite[i][jj] * C + (co < C ? co : 0)];
-              }
           }
-        }
-        f32x4 acc[TPW][NT];
-        kloop_n<EP, TPW>(nti, s_act, s_frag, s_nbt, rows, acc);
-        __syncthreads();
-        // next layer's fragments (after the last layer: the first layer's,
-        // for the next s') arrive while this layer's differences are formed
-        stage_async<NW * 64>(s_frag, fragp + (size_t)(l < n_layers ? l : 0) * per_fragp, per_fragp);
+          // the stored e^{2 z_l(s)} of the lane's rows, requested before the
+          // K loop so that the matrix work covers the memory latency
+          f32x4 za[TPW][NT];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-          if (i < nti) {
-            const int r0 = (wave + i * NW) * 16 + (lane >> 4) * 4;
+          for (int i = 0; i < NTILE; ++i)
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              if (r0 + jj < R) {
+            for (int nt = 0; nt < NT; ++nt)
+              za[i][nt] = *reinterpret_cast<const f32x4 *>(zl + site[i] * C + nt * 16 + 4 * (lane >> 4));
+          if (copy_next) stage_async_fixed<NW, K::FRAGP>(fnext, fsrc);
+          if constexpr (NTILE > 0) {
+            f32x4 acc[TPW][NT];
+            kloop_box<C, PREC, TPW, NTILE>(din, cap_in, fcur, ro, cf, acc);
+#pragma unroll
+            for (int i = 0; i < NTILE; ++i) {
+              const int r = (wave + i * NW) * 16 + (lane & 15);
+              if (r < R) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                  const int co = nt * 16 + (lane & 15);
-                  if (co < C) {
-                    const float dh = tanh_diff(za[i][jj][nt], acc[i][nt][jj]);
-                    if (l < n_layers) EP::store_act(s_act, osite[i][jj], co, dh);
-                    else part += (double)dh;
+                  float dh[4];
+#pragma unroll
+                  for (int jj = 0; jj < 4; ++jj) dh[jj] = tanh_diff(za[i][nt][jj], acc[i][nt][jj]);
+                  if (l < n_layers) {
+                    dstore4<C, PREC>(dout, cap_out, r, nt * 16 + 4 * (lane >> 4), dh);
+                  } else {
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) part += (double)dh[jj];
                   }
                 }
               }
             }
           }
+        };
+        with_tiles<TPW>(nti, body);
+        if (l == n_layers) {
+          part = wave_sum(part);
+          if (lane == 0) s_dl[(q & (K::SLOTS - 1)) * NW + wave] = part;
+          // with n even the last layer reads the even buffer: the next s'
+          // lift fills the odd one now
+          if (!(n_layers & 1) && q + 1 < total) lift(q + 1);
         }
-        if (l < n_layers) wait_copies();
+        wait_copies();
+        __syncthreads();
+        ++t;
+      }
+      if ((n_layers & 1) && q + 1 < total) {
+        lift(q + 1);
         __syncthreads();
       }
-      part = wave_sum(part);
-      if (lane == 0) s_dl[(q & 15) * NW + wave] = part;
     }
-    // the copy started by the last layer of the last s' must land before the
-    // next sample overwrites the buffer
-    wait_copies();
-    __syncthreads();
     if (tid == 0) {
       if (total > 0) flush(total, total - ((total - 1) & ~15));
       e_loc[b] = eacc;
@@ -441,6 +656,14 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
 
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
+template <int C, int PREC, int NW, int TPW>
+bool lc_fits(int L, int n) {
+  using K = LC<C, PREC, NW, TPW>;
+  int cap_odd, cap_even;
+  lc_caps(n, L, cap_odd, cap_even);
+  return L * L <= K::MR && cap_odd + cap_even + 2 <= K::ROWS;
+}
+
 // Launch shapes by lattice size: (waves per workgroup, row tiles per wave),
 // with NW * TPW * 16 >= N rows for the dense pass of s.  Eight waves (two
 // per SIMD) from 16x16 up, so that one wave's memory and barrier waits are
@@ -450,7 +673,7 @@ int lc_shape(int N) { return N <= 64 ? 0 : N <= 128 ? 1 : N <= 256 ? 2 : 3; }
 template <int C, int PREC, int NW, int TPW>
 int lc_grid(int B) {
   using K = LC<C, PREC, NW, TPW>;
-  const int lds = K::ACT + K::FRAG + 23 * K::MR + 256;
+  const int lds = K::REGION + K::FIXED + 256;
   int per_cu = 160 * 1024 / lds;
   const int thr = 2048 / (NW * 64);
   per_cu = per_cu < 1 ? 1 : (per_cu > thr ? thr : per_cu);
@@ -479,9 +702,12 @@ size_t lc_ws(const vqmc_model *m, int B) {
 template <int C, int PREC, int NW, int TPW>
 vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
                       int32_t *flags, double *lp, char *ws, hipStream_t st) {
-  // the workgroup's LDS rows hold one configuration's sites
-  if (m->L * m->L > LC<C, PREC, NW, TPW>::MR) return VQMC_ERR_SHAPE;
+  // the workgroup's LDS rows hold one configuration's sites, and the two
+  // difference buffers the boxes of distance 1 .. n
+  if (!lc_fits<C, PREC, NW, TPW>(m->L, m->n_layers)) return VQMC_ERR_SHAPE;
   const int n = m->n_layers;
+  int cap_odd, cap_even;
+  lc_caps(n, m->L, cap_odd, cap_even);
   char *f32 = ws;
   char *fp = ws + al256(n * frag_bytes_per_layer<C, P_F32>());
   float *z = reinterpret_cast<float *>(fp + al256(n * frag_bytes_per_layer<C, PREC>()));
@@ -491,7 +717,7 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
   if (PREC != P_F32) pack_layer_frags_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
   else fp = f32;
   eloc_lc_kernel<C, PREC, NW, TPW><<<lc_grid<C, PREC, NW, TPW>(B), NW * 64, 0, st>>>(
-      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, z, e_loc, flags, lp);
+      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, cap_odd, cap_even, z, e_loc, flags, lp);
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
   return VQMC_OK;
 }
@@ -525,7 +751,28 @@ size_t eloc_lc_workspace(const vqmc_model *m, int B) {
   }
 }
 
-bool eloc_lc_supported(const vqmc_model *m) { return m->channels == 16 || m->channels == 32; }
+template <int C, int PREC>
+bool lc_fits_c(int L, int n) {
+  switch (lc_shape(L * L)) {
+    case 0: return lc_fits<C, PREC, 4, 1>(L, n);
+    case 1: return lc_fits<C, PREC, 4, 2>(L, n);
+    case 2: return lc_fits<C, PREC, 8, 2>(L, n);
+    default: return PREC == P_F32 ? lc_fits<C, PREC, 8, 5>(L, n) : lc_fits<C, PREC, 12, 3>(L, n);
+  }
+}
+
+bool eloc_lc_supported(const vqmc_model *m) {
+  const int L = m->L, n = m->n_layers;
+  switch (m->channels) {
+    case 16:
+      return m->conv_prec == P_F32 ? lc_fits_c<16, P_F32>(L, n)
+             : m->conv_prec == P_BF16 ? lc_fits_c<16, P_BF16>(L, n) : lc_fits_c<16, P_X3>(L, n);
+    case 32:
+      return m->conv_prec == P_F32 ? lc_fits_c<32, P_F32>(L, n)
+             : m->conv_prec == P_BF16 ? lc_fits_c<32, P_BF16>(L, n) : lc_fits_c<32, P_X3>(L, n);
+    default: return false;
+  }
+}
 
 vqmc_status eloc_lc(const vqmc_model *m, const float *theta, const int8_t *spins, int B, double *e_loc,
                     int32_t *flags, double *lp, void *ws, hipStream_t st) {

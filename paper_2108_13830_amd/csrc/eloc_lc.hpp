@@ -8,7 +8,9 @@
 
 namespace vqmc {
 
-// Whether the light-cone kernel handles this model (C = 16 or 32).
+// Whether the light-cone kernel handles this model: C = 16 or 32, and the
+// cone boxes of distance 1 .. n fit the kernel's two LDS difference buffers
+// (at 24x24 in the split-BF16 and FP32 forms: n <= 8).
 bool eloc_lc_supported(const vqmc_model *m);
 
 // Device bytes of workspace for B samples: packed weight fragments and one

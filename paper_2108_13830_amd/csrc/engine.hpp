@@ -17,7 +17,10 @@
 // Matrix instructions (64-wide wavefronts, 16x16 output tiles):
 //   FP32   v_mfma_f32_16x16x4_f32   A: act[row=lane%16][k=4s+lane/16]
 //   BF16   v_mfma_f32_16x16x32_bf16 A: act[row=lane%16][k=32s+8(lane/16)+j]
-// both with D[row=4(lane/16)+i][col=lane%16], i = 0..3.
+// both with D[row=4(lane/16)+i][col=lane%16], i = 0..3.  With the operands
+// swapped the same instructions give the transposed tile (lane: four
+// consecutive channels of one row), which the BF16 forms and the light cone
+// use so that outputs leave in 4-channel pieces.
 // BF16X3 splits each operand into hi + lo BF16 parts and accumulates
 // hi*hi + hi*lo + lo*hi (three products per K-step) in FP32.
 #pragma once
@@ -73,6 +76,22 @@ __device__ __forceinline__ void stage_async(char *dst, const char *__restrict__ 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int c = wave; c < (bytes >> 10); c += NTHR / 64)
     __builtin_amdgcn_global_load_lds(src + (size_t)c * 1024 + lane * 16, (lds_ptr_t)(dst + c * 1024), 16, 0, 0);
+}
+
+// The same copy with a fixed, compile-time number of loads per wave
+// (ceil(chunks / NW); waves past the last chunk copy it again: the same
+// bytes to the same place).  A fixed count lets the compiler wait for loads
+// issued before the copy without waiting for the copy itself.
+template <int NW, int BYTES>
+__device__ __forceinline__ void stage_async_fixed(char *dst, const char *__restrict__ src) {
+  constexpr int CH = BYTES >> 10, PER = (CH + NW - 1) / NW;
+  static_assert(BYTES % 1024 == 0 && CH > 0, "copies move whole 1 KiB pieces");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int c = wave + p * NW < CH ? wave + p * NW : CH - 1;
+    __builtin_amdgcn_global_load_lds(src + (size_t)c * 1024 + lane * 16, (lds_ptr_t)(dst + c * 1024), 16, 0, 0);
+  }
 }
 
 // Waits for this thread's outstanding memory operations (the direct-to-LDS
@@ -132,6 +151,31 @@ struct Engine {
       return row * C + ((((c >> 3) ^ ((row >> RSH) & (C / 8 - 1))) << 3) | (c & 7));
     } else {
       return row * C + c;
+    }
+  }
+
+  // Four consecutive channels co0..co0+3 of one row (co0 a multiple of 4):
+  // one 8-byte store per BF16 plane (the four lie in one swizzled 8-group).
+  __device__ static __forceinline__ void store_act4(char *act, int row, int co0, const float (&h)[4]) {
+    if constexpr (F32) {
+      float *p = reinterpret_cast<float *>(act) + row * LDA + co0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) p[j] = h[j];
+    } else {
+      uint16_t *hi = reinterpret_cast<uint16_t *>(act);
+      const int pi = phys(row, co0);
+      uint16_t b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = bf16_rne(h[j]);
+      *reinterpret_cast<uint2 *>(hi + pi) =
+          uint2{(uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16)};
+      if constexpr (X3) {
+        uint16_t c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = bf16_rne(h[j] - bf16_f32(b[j]));
+        *reinterpret_cast<uint2 *>(hi + MAXROWS * C + pi) =
+            uint2{(uint32_t)c[0] | ((uint32_t)c[1] << 16), (uint32_t)c[2] | ((uint32_t)c[3] << 16)};
+      }
     }
   }
 
@@ -350,7 +394,8 @@ struct Engine {
   }
 
   // Lift layer on the FP32 matrix cores: K = 9 taps padded to 12,
-  // A[row][tap] = s[nb(row, tap)] (exact +-1), B[tap][co] = W0[co][tap].
+  // A[row][tap] = s[nb(row, tap)] (exact +-1), B[tap][co] = W0[co][tap],
+  // in the forward pass's tile orientation.
   __device__ static __forceinline__ void lift_tab(const float *__restrict__ theta, const int8_t *sp,
                                                   const uint16_t *nbt, int R, char *act) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -377,27 +422,35 @@ struct Engine {
         const int row = (wave + i * NW) * 16 + (lane & 15);
         const float a = (float)sp[nbt[kk * MAXROWS + row]];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(kv ? a : 0.f, b[nt], acc[i][nt]);
+        for (int nt = 0; nt < NT; ++nt)
+          acc[i][nt] = FWD_TR ? mma_f32(b[nt], kv ? a : 0.f, acc[i][nt]) : mma_f32(kv ? a : 0.f, b[nt], acc[i][nt]);
       }
     }
-    write_tiles(acc, theta + 9 * C, R, act, nullptr);
+    write_fwd(acc, theta + 9 * C, R, act);
   }
 
   // K loop of one C -> C layer over the wave's row tiles with the gather
   // rows read from the neighbour table; results stay in acc.
+  template <bool TR = false>
   __device__ static __forceinline__ void kloop_tab(const char *act, const char *frag, const uint16_t *nbt,
                                                    f32x4 (&acc)[TPW][NT]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int rowi[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) rowi[i] = (wave + i * NW) * 16 + (lane & 15);
-    kloop_rows<TPW>(act, frag, nbt, rowi, acc);
+    kloop_rows<TPW, TR>(act, frag, nbt, rowi, acc);
   }
 
   // The same K loop for tile i of this wave reading the lane's table column
   // rowi[i] (the output row's own index into nbt); only the first NTILE tile
   // slots are computed (compile time).
-  template <int NTILE>
+  // TR: the product is formed transposed, out^T = W^T act^T, by passing the
+  // weight fragments as the instruction's first operand (the per-lane
+  // layouts of the two operands coincide).  Then acc[i][nt][j] is
+  // out[row = 16 T + lane%16][co = 16 nt + 4 (lane/16) + j]: every lane holds
+  // four consecutive channels of one row, written with one wide store, and
+  // the row is the one the lane gathers for.
+  template <int NTILE, bool TR = false>
   __device__ static __forceinline__ void kloop_rows(const char *act, const char *frag, const uint16_t *nbt,
                                                     const int (&rowi)[TPW], f32x4 (&acc)[TPW][NT]) {
     const int lane = threadIdx.x & 63;
@@ -427,7 +480,8 @@ struct Engine {
 #pragma unroll
           for (int i = 0; i < NTILE; ++i)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mma_f32(a[i], b[nt], acc[i][nt]);
+            for (int nt = 0; nt < NT; ++nt)
+              acc[i][nt] = TR ? mma_f32(b[nt], a[i], acc[i][nt]) : mma_f32(a[i], b[nt], acc[i][nt]);
         }
       }
     } else {
@@ -458,10 +512,18 @@ struct Engine {
         for (int i = 0; i < NTILE; ++i)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
-            acc[i][nt] = mma_bf16(ah[i], bh[nt], acc[i][nt]);
-            if constexpr (X3) {
-              acc[i][nt] = mma_bf16(ah[i], bl[nt], acc[i][nt]);
-              acc[i][nt] = mma_bf16(al[i], bh[nt], acc[i][nt]);
+            if constexpr (TR) {
+              acc[i][nt] = mma_bf16(bh[nt], ah[i], acc[i][nt]);
+              if constexpr (X3) {
+                acc[i][nt] = mma_bf16(bl[nt], ah[i], acc[i][nt]);
+                acc[i][nt] = mma_bf16(bh[nt], al[i], acc[i][nt]);
+              }
+            } else {
+              acc[i][nt] = mma_bf16(ah[i], bh[nt], acc[i][nt]);
+              if constexpr (X3) {
+                acc[i][nt] = mma_bf16(ah[i], bl[nt], acc[i][nt]);
+                acc[i][nt] = mma_bf16(al[i], bh[nt], acc[i][nt]);
+              }
             }
           }
       }
@@ -487,6 +549,57 @@ struct Engine {
             const float h = tanh_f(acc[i][nt][j] + bv);
             store_act(act, row, co, h);
             if (scratch) scratch[row * C + co] = h;
+          }
+        }
+      }
+    }
+  }
+
+  // write_tiles for transposed tiles (TR above): tanh(acc + bias) of four
+  // consecutive channels per lane and row, one wide store each.
+  __device__ static __forceinline__ void write_tiles_t(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
+                                                       char *act) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co0 = nt * 16 + 4 * (lane >> 4);
+      if (co0 < C) {
+        float bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bias[co0 + j];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int row = (wave + i * NW) * 16 + (lane & 15);
+          if (row < R) {
+            float h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h[j] = tanh_f(acc[i][nt][j] + bv[j]);
+            store_act4(act, row, co0, h);
+          }
+        }
+      }
+    }
+  }
+
+  // head_vals for transposed tiles.
+  __device__ static __forceinline__ void head_vals_t(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
+                                                     float *hv) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co0 = nt * 16 + 4 * (lane >> 4);
+      if (co0 < C) {
+        float bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bias[co0 + j];
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          const int row = (wave + i * NW) * 16 + (lane & 15);
+          if (row < R) {
+            f32x4 h;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) h[j] = tanh_f(acc[i][nt][j] + bv[j]);
+            *reinterpret_cast<f32x4 *>(hv + row * C + co0) = h;
           }
         }
       }
@@ -523,6 +636,16 @@ struct Engine {
   // written.  Without it the weights are staged from theta.
   static constexpr int FRAG_LAYER = KS * NT * 64 * FRAG;
   static constexpr bool DMA_OK = FRAG_LAYER % 1024 == 0;
+  // Tile orientation of the forward pass: transposed for the BF16 forms,
+  // whose per-output work (tanh, rounding, 16-bit stores) outweighs their
+  // matrix work at these channel counts; FP32 keeps the row-major tiles,
+  // which measured faster there (scalar stores either way).
+  static constexpr bool FWD_TR = !F32;
+  __device__ static __forceinline__ void write_fwd(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
+                                                   char *act) {
+    if constexpr (FWD_TR) write_tiles_t(acc, bias, R, act);
+    else write_tiles(acc, bias, R, act, nullptr);
+  }
   __device__ static __forceinline__ void forward(const float *__restrict__ theta, int n_layers, const int8_t *sp,
                                                  int G, int N, char *smem_act, char *smem_frag,
                                                  const uint16_t *nbt, double *lp,
@@ -536,18 +659,20 @@ struct Engine {
     __syncthreads();
     for (int l = 1; l <= n_layers; ++l) {
       f32x4 acc[TPW][NT];
-      kloop_tab(smem_act, smem_frag, nbt, acc);
+      kloop_tab<FWD_TR>(smem_act, smem_frag, nbt, acc);
       __syncthreads();
       const float *bias = theta + layer_offset(C, l) + 9 * C * C;
       if (l < n_layers) {
         if (dma) {
           stage_async<NTHR>(smem_frag, packed + (size_t)l * FRAG_LAYER, FRAG_LAYER);
-          write_tiles(acc, bias, R, smem_act, nullptr);
+          write_fwd(acc, bias, R, smem_act);
           wait_copies();
         } else {
-          write_tiles(acc, bias, R, smem_act, nullptr);
+          write_fwd(acc, bias, R, smem_act);
           stage_weights(theta + layer_offset(C, l + 1), smem_frag);
         }
+      } else if constexpr (FWD_TR) {
+        head_vals_t(acc, bias, R, reinterpret_cast<float *>(smem_act));
       } else {
         head_vals(acc, bias, R, reinterpret_cast<float *>(smem_act));
       }
