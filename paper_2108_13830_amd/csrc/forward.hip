@@ -186,7 +186,7 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void logpsi_kernel(const 
 // engine in batches of G, and the off-diagonal terms J/2 mu exp(dlog) are
 // accumulated in FP64 in bond order.
 template <int C, int PREC, int NW, int TPW>
-__global__ __launch_bounds__(NW * 64, C <= 16 ? 2 : 1) void eloc_kernel(const float *__restrict__ theta,
+__global__ __launch_bounds__(NW * 64, C <= 16 ? (TPW <= 7 ? 3 : 2) : 1) void eloc_kernel(const float *__restrict__ theta,
                                                        const int8_t *__restrict__ spins, int B, int L,
                                                        int n_layers, double J1, double J2,
                                                        int marshall, int G,
@@ -467,6 +467,11 @@ struct Inst {
   static constexpr int TPW = (C == 32) ? 9 : 8;  // rows per block: 576 / 512
   static constexpr int SNW = 1;                   // sampler, small lattices
   static constexpr int STPW = 9;                  // 144 rows
+  // dense local energy in the BF16 forms at C = 16: 448 rows, so that three
+  // workgroups share a compute unit (their per-output work then overlaps
+  // each other's matrix work); used while a configuration fits (FP32
+  // measured faster with 512 rows and two workgroups)
+  static constexpr int ETPW = 7;
 };
 
 enum Kind { K_LOGPSI, K_ELOC, K_SAMPLE };
@@ -535,9 +540,21 @@ static vqmc_status launch(Kind kind, const FwdArgs &a) {
       pack_layer_frags_kernel<C, PREC><<<(total + 255) / 256, 256, 0, a.stream>>>(a.theta, a.n_layers, a.ws);
       packed = a.ws;
     }
-    eloc_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
-        a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i, a.lp_out,
-        packed);
+    bool done = false;
+    if constexpr (C == 16 && PREC != P_F32) {
+      using E7 = Engine<C, PREC, I::NW, I::ETPW>;
+      if (N <= E7::MAXROWS) {
+        const int G7 = E7::MAXROWS / N < 64 ? E7::MAXROWS / N : 64;
+        eloc_kernel<C, PREC, I::NW, I::ETPW><<<a.B, I::NW * 64, 0, a.stream>>>(
+            a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G7, a.out_d, a.out_i, a.lp_out,
+            packed);
+        done = true;
+      }
+    }
+    if (!done)
+      eloc_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
+          a.theta, a.spins_in, a.B, a.L, a.n_layers, a.J1, a.J2, a.marshall, G, a.out_d, a.out_i, a.lp_out,
+          packed);
   }
   VQMC_LAUNCH_CHECK();
   return VQMC_OK;
