@@ -665,9 +665,10 @@ bool lc_fits(int L, int n) {
 }
 
 // Launch shapes by lattice size: (waves per workgroup, row tiles per wave),
-// with NW * TPW * 16 >= N rows for the dense pass of s.  Eight waves (two
-// per SIMD) from 16x16 up, so that one wave's memory and barrier waits are
-// covered by the other's matrix work.
+// with NW * TPW * 16 >= N rows for the dense pass of s.  Twelve waves (three
+// per SIMD) above 128 sites, so that one wave's memory and barrier waits are
+// covered by the others' work (measured against eight waves at 16x16 and
+// 24x24).
 int lc_shape(int N) { return N <= 64 ? 0 : N <= 128 ? 1 : N <= 256 ? 2 : 3; }
 
 template <int C, int PREC, int NW, int TPW>
@@ -686,8 +687,8 @@ int lc_grid_c(int N, int B) {
   switch (lc_shape(N)) {
     case 0: return lc_grid<C, PREC, 4, 1>(B);
     case 1: return lc_grid<C, PREC, 4, 2>(B);
-    case 2: return lc_grid<C, PREC, 8, 2>(B);
-    default: return PREC == P_F32 ? lc_grid<C, PREC, 8, 5>(B) : lc_grid<C, PREC, 12, 3>(B);
+    case 2: return lc_grid<C, PREC, 12, 2>(B);
+    default: return lc_grid<C, PREC, 12, 3>(B);
   }
 }
 
@@ -728,12 +729,9 @@ vqmc_status lc_launch_c(const vqmc_model *m, const float *theta, const int8_t *s
   switch (lc_shape(m->L * m->L)) {
     case 0: return lc_launch<C, PREC, 4, 1>(m, theta, spins, B, e_loc, flags, lp, ws, st);
     case 1: return lc_launch<C, PREC, 4, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
-    case 2: return lc_launch<C, PREC, 8, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
-    // BF16 forms: 12 waves of 3 tiles (more waves to hide the cone's latencies);
-    // FP32: 8 waves of 5 tiles
+    case 2: return lc_launch<C, PREC, 12, 2>(m, theta, spins, B, e_loc, flags, lp, ws, st);
     default:
-      return PREC == P_F32 ? lc_launch<C, PREC, 8, 5>(m, theta, spins, B, e_loc, flags, lp, ws, st)
-                           : lc_launch<C, PREC, 12, 3>(m, theta, spins, B, e_loc, flags, lp, ws, st);
+      return lc_launch<C, PREC, 12, 3>(m, theta, spins, B, e_loc, flags, lp, ws, st);
   }
 }
 
@@ -756,8 +754,8 @@ bool lc_fits_c(int L, int n) {
   switch (lc_shape(L * L)) {
     case 0: return lc_fits<C, PREC, 4, 1>(L, n);
     case 1: return lc_fits<C, PREC, 4, 2>(L, n);
-    case 2: return lc_fits<C, PREC, 8, 2>(L, n);
-    default: return PREC == P_F32 ? lc_fits<C, PREC, 8, 5>(L, n) : lc_fits<C, PREC, 12, 3>(L, n);
+    case 2: return lc_fits<C, PREC, 12, 2>(L, n);
+    default: return lc_fits<C, PREC, 12, 3>(L, n);
   }
 }
 
