@@ -3,13 +3,17 @@
 // (Sec. 3.2.2: the Cholesky factor followed by forward and back substitution
 // instead of an explicit inverse of M).
 //
-// Right-looking, two block levels: 512-column outer panels, each factored as
-// eight 64-column sub-panels.  Per sub-panel: one workgroup factors the 64 x 64
-// diagonal block and, in the same sweep, inverts its triangle; the rows below
-// are then one GEMM with that small inverse; the rest of the outer panel is
-// updated.  After each outer panel the trailing matrix receives one rank-512
-// update on the FP64 matrix cores, so it is read and written once per 512
-// columns.
+// Two block levels: 512-column outer panels, right-looking between them (after
+// each outer panel the trailing matrix receives one rank-512 update on the
+// FP64 matrix cores, so it is read and written once per 512 columns), and
+// left-looking inside them over 64-column sub-panels.  A workgroup factors a
+// 64 x 64 diagonal block and, in the same sweep, inverts its triangle; the
+// rows below are then one GEMM with that small inverse.  One launch per
+// sub-panel after the first does the previous sub-panel's row solve, the
+// left-looking update of its own columns and the factorisation of its own
+// diagonal block (by the workgroup that updated it), so that the chain of
+// dependent launches, which competes with the concurrent trailing update for
+// compute units, is one launch per 64 columns.
 //
 // The right-hand side rides along as an extra last row of the matrix: the
 // factorisation of [[M, r], [r^T, *]] leaves y = L^-1 r in that row, so the
@@ -69,9 +73,9 @@ __device__ __forceinline__ double recip(double d) {
 // column j+1 update and publish it first, and everyone finishes the other
 // columns of step j after the barrier.  Rows past n are padded with the
 // identity.
-__global__ __launch_bounds__(256) void chol_diag_kernel(double *__restrict__ M, int64_t n, int64_t ld, int64_t c0,
-                                                       double *__restrict__ Linv, int *__restrict__ status) {
-  __shared__ double colbuf[2][CB];
+__device__ __forceinline__ void diag_factor(double *__restrict__ M, int64_t n, int64_t ld, int64_t c0,
+                                            double *__restrict__ Linv, int *__restrict__ status,
+                                            double (*colbuf)[CB]) {
   const int tid = threadIdx.x, bx = tid >> 4, by = tid & 15;
   const int x0 = 4 * bx, y0 = 4 * by;
   const int m = (int)((n - c0) < CB ? (n - c0) : CB);
@@ -161,6 +165,21 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(double *__restrict__ M, 
   }
 }
 
+// side (nullable): receives rows c0 + 64 .. c0 + 127 of the block's columns
+// as they are before this sub-panel's row solve (rows past the last one of the
+// augmented matrix repeat it).
+__global__ __launch_bounds__(256) void chol_diag_kernel(double *__restrict__ M, int64_t n, int64_t ld, int64_t c0,
+                                                       double *__restrict__ Linv, int *__restrict__ status,
+                                                       double *__restrict__ side) {
+  __shared__ double colbuf[2][CB];
+  if (side)
+    for (int idx = threadIdx.x; idx < CB * CB; idx += 256) {
+      const int r = idx >> 6, t = idx & 63;
+      side[idx] = M[clamp_row(c0 + CB + r, n + 1) * ld + c0 + t];
+    }
+  diag_factor(M, n, ld, c0, Linv, status, colbuf);
+}
+
 // Stage a 64 x 64 block of doubles (rows r0.. clamped to nr, columns
 // k0..k0+63) into LDS: 8 16-byte loads per thread, all issued before the
 // first store.
@@ -197,29 +216,66 @@ __device__ __forceinline__ void stage64_partial(const double *__restrict__ src, 
 }
 
 // Rows below the diagonal block of width m: L[r][c0..c0+m) = A[r][c0..] Linv^T
+// Stages rows r0 .. r0+63 of src (clamped to nr - 1), columns k0 .. k0+31,
+// into dst; columns at or past kend are zero (FULL: all 32 are inside).
+constexpr int KH = 32;  // K chunk of the panel kernels (34.8 KB of LDS for two tiles)
+template <bool FULL>
+__device__ __forceinline__ void stage32(const double *__restrict__ src, int64_t ld, int64_t r0, int64_t nr,
+                                        int64_t k0, int64_t kend, double (*dst)[KH + 2]) {
+  if constexpr (FULL) {
+    f64x2 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 4, j = idx & 15;
+      v[q] = *reinterpret_cast<const f64x2 *>(src + clamp_row(r0 + r, nr) * ld + k0 + 2 * j);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 4, j = idx & 15;
+      *reinterpret_cast<f64x2 *>(&dst[r][2 * j]) = v[q];
+    }
+  } else {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, t = idx & 31;
+      const int64_t c = k0 + t < kend ? k0 + t : kend - 1;
+      v[q] = src[clamp_row(r0 + r, nr) * ld + c];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, t = idx & 31;
+      dst[r][t] = k0 + t < kend ? v[q] : 0.0;
+    }
+  }
+}
+
 // for r in [c0+m, nr), 64 rows per workgroup (4 waves x 16 rows, 4 column
 // tiles each).  The last row of the augmented matrix is included, so this is
 // also the forward substitution step of that block.
 template <bool FULL>
 __global__ __launch_bounds__(256) void chol_trsm_kernel(double *__restrict__ M, int64_t nr, int64_t ld, int64_t c0,
                                                        int m, const double *__restrict__ Linv) {
-  __shared__ double sA[CB][CB + 2];
-  __shared__ double sL[CB][CB + 2];
+  __shared__ double sA[CB][KH + 2];
+  __shared__ double sL[CB][KH + 2];
   const int64_t r0 = c0 + m + (int64_t)blockIdx.x * CB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if constexpr (FULL) stage64(M, ld, r0, nr, c0, sA);
-  else stage64_partial(M, ld, r0, nr, c0, m, sA);
-  stage64(Linv, CB, 0, CB, 0, sL);
-  __syncthreads();
   f64x4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = f64x4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int ks = 0; ks < CB / 4; ++ks) {
-    const int k = ks * 4 + (lane >> 4);
-    const double a = sA[wave * 16 + (lane & 15)][k];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = mma64(a, sL[q * 16 + (lane & 15)][k], acc[q]);
+  for (int h = 0; h < CB / KH; ++h) {
+    stage32<FULL>(M, ld, r0, nr, c0 + KH * h, c0 + m, sA);
+    stage32<true>(Linv, CB, 0, CB, KH * h, CB, sL);
+    __syncthreads();
+#pragma unroll 4
+    for (int ks = 0; ks < KH / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      const double a = sA[wave * 16 + (lane & 15)][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = mma64(a, sL[q * 16 + (lane & 15)][k], acc[q]);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q)
@@ -231,57 +287,156 @@ __global__ __launch_bounds__(256) void chol_trsm_kernel(double *__restrict__ M, 
     }
 }
 
-// Remaining columns of the outer panel after sub-panel c0, one 64 x 64 tile
-// per workgroup: A[r][c] -= sum_t L[r][c0+t] L[c][c0+t] for c in
-// [c0+64, cend), r >= c, r < nr.
-__global__ __launch_bounds__(256) void chol_panel_update_kernel(double *__restrict__ M, int64_t nr, int64_t ld,
-                                                                int64_t c0, int64_t cend) {
-  __shared__ double sR[CB][CB + 2];
-  __shared__ double sC[CB][CB + 2];
-  const int64_t cc0 = c0 + CB + (int64_t)blockIdx.x * CB;
-  const int64_t r0 = c0 + CB + (int64_t)blockIdx.y * CB;
-  if (cc0 > r0 + CB - 1) return;  // tile strictly above the diagonal (uniform per workgroup)
+// One step of the factorisation of an outer panel [p0, ...): the row solve
+// of sub-panel c0 (whose diagonal block is factored, its inverse in Linv0)
+// fused with the left-looking update and the factorisation of the next
+// sub-panel c1 = c0 + 64.  Workgroup b takes rows R = [c1 + 64 b, +64):
+//   1. L0[R] = M[R][c0 blk] Linv0^T (written to M), and, recomputed by every
+//      workgroup, L0[C] for the rows C = [c1, +64) from side_in (the values
+//      of M[C][c0 blk] before this launch, which workgroup 0 overwrites);
+//   2. M[R][c] -= sum_{k in [p0, c1)} L[R][k] L[C][k] for c in [c1, cend),
+//      r >= c, r < nr: the c0 block from 1., earlier blocks from M;
+//      workgroup 1 also copies its updated rows to side_out for the next step;
+//   3. workgroup 0 factors the diagonal block of c1 (inverse into Linv1).
+__global__ __launch_bounds__(256) void chol_step_kernel(double *__restrict__ M, int64_t nr, int64_t ld, int64_t p0,
+                                                        int64_t c0, int64_t cend,
+                                                        const double *__restrict__ Linv0,
+                                                        double *__restrict__ Linv1, int *__restrict__ status,
+                                                        const double *__restrict__ side_in,
+                                                        double *__restrict__ side_out) {
+  __shared__ double sX[CB][CB + 2];
+  __shared__ double sY[CB][CB + 2];
+  __shared__ double colbuf[2][CB];
+  const int64_t c1 = c0 + CB;
+  const int64_t r0 = c1 + (int64_t)blockIdx.x * CB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  stage64(M, ld, r0, nr, c0, sR);
-  stage64(M, ld, cc0, nr, c0, sC);
+  // ---- 1. row solve of sub-panel c0 for R and C, in two 32-column halves:
+  // sX[.][0, 32) = M[R] half, sX[.][34, 66) = Linv0 half, sY[.][0, 32) = side_in half
+  f64x4 aR[4], aC[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) aR[q] = aC[q] = f64x4{0, 0, 0, 0};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 4, j = idx & 15;
+      const f64x2 vr = *reinterpret_cast<const f64x2 *>(M + clamp_row(r0 + r, nr) * ld + c0 + KH * h + 2 * j);
+      const f64x2 vl = *reinterpret_cast<const f64x2 *>(Linv0 + r * CB + KH * h + 2 * j);
+      const f64x2 vc = *reinterpret_cast<const f64x2 *>(side_in + r * CB + KH * h + 2 * j);
+      *reinterpret_cast<f64x2 *>(&sX[r][2 * j]) = vr;
+      *reinterpret_cast<f64x2 *>(&sX[r][KH + 2 + 2 * j]) = vl;
+      *reinterpret_cast<f64x2 *>(&sY[r][2 * j]) = vc;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ks = 0; ks < KH / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      const double ar = sX[wave * 16 + (lane & 15)][k];
+      const double ac = sY[wave * 16 + (lane & 15)][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double l = sX[q * 16 + (lane & 15)][KH + 2 + k];
+        aR[q] = mma64(ar, l, aR[q]);
+        aC[q] = mma64(ac, l, aC[q]);
+      }
+    }
+    __syncthreads();
+  }
+  // L0[R] to M and to sX, L0[C] to sY (row-major [row][k], k in the c0 block)
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lr = wave * 16 + (lane >> 4) + 4 * r, col = q * 16 + (lane & 15);
+      const int64_t row = r0 + lr;
+      if (row < nr) M[row * ld + c0 + col] = aR[q][r];
+      sX[lr][col] = aR[q][r];
+      sY[lr][col] = aC[q][r];
+    }
   __syncthreads();
+  // ---- 2. left-looking update of the c1 block: first the c0 block ...
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
-#pragma unroll 4
-  for (int ks = 0; ks < CB / 4; ++ks) {
-    const int k = ks * 4 + (lane >> 4);
-    double a[2], b[2];
+  auto mma_block = [&](int kw) {
+    for (int ks = 0; ks < kw / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      double a[2], b[2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      a[t] = sR[wm * 32 + t * 16 + (lane & 15)][k];
-      b[t] = sC[wn * 32 + t * 16 + (lane & 15)][k];
+      for (int t = 0; t < 2; ++t) {
+        a[t] = sX[wm * 32 + t * 16 + (lane & 15)][k];
+        b[t] = sY[wn * 32 + t * 16 + (lane & 15)][k];
+      }
+#pragma unroll
+      for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn) acc[tm][tn] = mma64(a[tm], b[tn], acc[tm][tn]);
     }
+  };
+  mma_block(CB);
+  __syncthreads();
+  // ... then the earlier blocks of the outer panel, 64 columns at a time
+  // (the next chunk loaded into registers while the current one is used)
+  auto load = [&](f64x2 (&v)[8], int64_t rb, int64_t k0) {
 #pragma unroll
-    for (int tm = 0; tm < 2; ++tm)
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, j = idx & 31;
+      v[q] = *reinterpret_cast<const f64x2 *>(M + clamp_row(rb + r, nr) * ld + k0 + 2 * j);
+    }
+  };
+  auto store = [&](const f64x2 (&v)[8], double (*dst)[CB + 2]) {
 #pragma unroll
-      for (int tn = 0; tn < 2; ++tn) acc[tm][tn] = mma64(a[tm], b[tn], acc[tm][tn]);
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, j = idx & 31;
+      *reinterpret_cast<f64x2 *>(&dst[r][2 * j]) = v[q];
+    }
+  };
+  if (c0 > p0) {
+    f64x2 vr[8], vc[8];
+    load(vr, r0, p0);
+    load(vc, c1, p0);
+    for (int64_t k0 = p0; k0 < c0; k0 += CB) {
+      store(vr, sX);
+      store(vc, sY);
+      __syncthreads();
+      if (k0 + CB < c0) {
+        load(vr, r0, k0 + CB);
+        load(vc, c1, k0 + CB);
+      }
+      mma_block(CB);
+      __syncthreads();
+    }
   }
+  // M[R][c1 blk] -= acc (lower triangle, existing rows and columns)
 #pragma unroll
   for (int tm = 0; tm < 2; ++tm)
 #pragma unroll
     for (int tn = 0; tn < 2; ++tn) {
-      const int64_t col = cc0 + wn * 32 + tn * 16 + (lane & 15);
+      const int lc = wn * 32 + tn * 16 + (lane & 15);
+      const int64_t col = c1 + lc;
       double cur[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t row = r0 + wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
-        cur[r] = M[clamp_row(row, nr) * ld + (col < cend ? col : c0)];
+        cur[r] = M[clamp_row(row, nr) * ld + (col < cend ? col : c1)];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
-        if (row < nr && col < cend && col <= row) M[row * ld + col] = cur[r] - acc[tm][tn][r];
+        const int lr = wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
+        const int64_t row = r0 + lr;
+        const double v = cur[r] - acc[tm][tn][r];
+        if (row < nr && col < cend && col <= row) M[row * ld + col] = v;
+        if (blockIdx.x == 1 && side_out) side_out[lr * CB + lc] = v;
       }
     }
+  // ---- 3. the workgroup of the diagonal block factors it
+  if (blockIdx.x == 0) {
+    __syncthreads();
+    diag_factor(M, nr - 1, ld, c1, Linv1, status, colbuf);
+  }
 }
 
 // Loader of the trailing update: rows ra0.. (A side) or rb0.. (B side) of M,
@@ -320,7 +475,7 @@ struct TrailLoader {
 // triangle of block rows and columns >= OB / 128 (the rest).
 __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restrict__ M, int64_t n, int64_t nr,
                                                             int64_t ld, int64_t p0, int64_t p1, int ntiles,
-                                                            int ncb) {
+                                                            int ncb, int nchunks) {
   constexpr int KC = 16;
   __shared__ Panel<double, KC, false> sA, sB;
   using TT = Tile128<double>;
@@ -341,7 +496,7 @@ __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restric
   TrailLoader<KC> ldr{M, ld, nr, r0, c0, p0};
   TT::acc_t acc[4][4];
   TT::zero(acc);
-  TT::run<KC, false>(ldr, OB / KC, sA, sB, acc);
+  TT::run<KC, false>(ldr, nchunks, sA, sB, acc);
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
@@ -445,7 +600,9 @@ __global__ __launch_bounds__(256) void chol_bwd_update_kernel(const double *__re
 
 size_t chol_workspace_bytes(int64_t n) {
   const int64_t nb = (n + CB - 1) / CB;
-  return (size_t)nb * CB * CB * 8;
+  // the inverses of the diagonal blocks, then two 64 x 64 blocks of rows
+  // carried from one step of a panel to the next
+  return (size_t)(nb + 2) * CB * CB * 8;
 }
 
 // A second stream and two events per device, created on first use and kept
@@ -488,37 +645,47 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
   bool rest_pending = false;
   for (int64_t p0 = 0; p0 < n; p0 += OB) {
     const int64_t p1 = (p0 + OB) < n ? p0 + OB : n;
-    for (int64_t c0 = p0; c0 < p1; c0 += CB) {
-      double *Li = Linv + (c0 / CB) * CB * CB;
-      const int m = (int)((n - c0) < CB ? (n - c0) : CB);
-      chol_diag_kernel<<<1, 256, 0, st>>>(M, n, ld, c0, Li, status);
-      const int64_t below = nr - (c0 + m);
+    // first sub-panel: factor its diagonal block (keeping the rows below
+    // it for the next step); then one launch per further sub-panel, each
+    // solving the previous sub-panel's rows and updating (left-looking inside
+    // the panel) and factoring its own; last, the rows of the last sub-panel
+    double *side = Linv + ((n + CB - 1) / CB) * CB * CB;
+    chol_diag_kernel<<<1, 256, 0, st>>>(M, n, ld, p0, Linv + (p0 / CB) * CB * CB, status,
+                                        p0 + CB < p1 ? side : nullptr);
+    int64_t cl = p0;
+    for (int64_t c1 = p0 + CB; c1 < p1; c1 += CB) {
+      const int64_t c0 = c1 - CB, m1 = (n - c1) < CB ? (n - c1) : CB;
+      const int j = (int)((c0 - p0) / CB);
+      chol_step_kernel<<<(unsigned)((nr - c1 + CB - 1) / CB), 256, 0, st>>>(
+          M, nr, ld, p0, c0, c1 + m1, Linv + (c0 / CB) * CB * CB, Linv + (c1 / CB) * CB * CB, status,
+          side + (j & 1) * CB * CB, c1 + CB < p1 ? side + ((j + 1) & 1) * CB * CB : nullptr);
+      cl = c1;
+    }
+    {
+      const int m = (int)((n - cl) < CB ? (n - cl) : CB);
+      const int64_t below = nr - (cl + m);
+      double *Li = Linv + (cl / CB) * CB * CB;
       if (m == CB)
-        chol_trsm_kernel<true><<<(unsigned)((below + CB - 1) / CB), 256, 0, st>>>(M, nr, ld, c0, m, Li);
+        chol_trsm_kernel<true><<<(unsigned)((below + CB - 1) / CB), 256, 0, st>>>(M, nr, ld, cl, m, Li);
       else
-        chol_trsm_kernel<false><<<(unsigned)((below + CB - 1) / CB), 256, 0, st>>>(M, nr, ld, c0, m, Li);
-      const int64_t rest = p1 - (c0 + CB);
-      if (rest > 0) {
-        const dim3 g((unsigned)((rest + CB - 1) / CB), (unsigned)((below + CB - 1) / CB));
-        chol_panel_update_kernel<<<g, 256, 0, st>>>(M, nr, ld, c0, p1);
-      }
+        chol_trsm_kernel<false><<<(unsigned)((below + CB - 1) / CB), 256, 0, st>>>(M, nr, ld, cl, m, Li);
     }
     if (p1 >= n) break;
     const int T = (int)((nr - p1 + 127) / 128);
     const int ncb = T < OB / 128 ? T : OB / 128;  // block columns of the next outer panel
     // the next panel's columns must also have the previous rest update
     if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
-    chol_trailing_kernel<<<(unsigned)(T * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, T * ncb, ncb);
+    chol_trailing_kernel<<<(unsigned)(T * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, T * ncb, ncb, OB / 16);
     if (T > ncb) {
       const int nt = (T - ncb) * (T - ncb + 1) / 2;
       if (sd) {
         if (hipEventRecord(sd->next, st) != hipSuccess || hipStreamWaitEvent(sd->s, sd->next, 0) != hipSuccess)
           return VQMC_ERR_DEVICE;
-        chol_trailing_kernel<<<(unsigned)nt, 256, 0, sd->s>>>(M, n, nr, ld, p0, p1, nt, 0);
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, sd->s>>>(M, n, nr, ld, p0, p1, nt, 0, OB / 16);
         if (hipEventRecord(sd->rest, sd->s) != hipSuccess) return VQMC_ERR_DEVICE;
         rest_pending = true;
       } else {
-        chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt, 0);
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt, 0, OB / 16);
       }
     }
   }
