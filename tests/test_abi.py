@@ -77,6 +77,19 @@ def test_argument_errors_need_no_gpu():
     auto10 = V.Model(10, 16, 6).c()
     assert lib.vqmc_local_energy_method(ct.byref(auto10), ct.byref(meth)) == 0 and meth.value == V.ELOC_DENSE
     assert lib.vqmc_local_energy_method(ct.byref(lc4), ct.byref(meth)) == 1
+    # the light cone keeps the boxes of distance 1 .. n in two LDS buffers: at
+    # 24 x 24 the split-BF16 and FP32 forms fit n <= 8 (the dense evaluation
+    # is used beyond), the single-BF16 form any n
+    for prec, n_layers, want in ((V.PREC_BF16X3, 8, V.ELOC_LIGHTCONE), (V.PREC_BF16X3, 9, V.ELOC_DENSE),
+                                 (V.PREC_FP32, 9, V.ELOC_DENSE), (V.PREC_BF16, 16, V.ELOC_LIGHTCONE)):
+        mm = V.Model(24, 32, n_layers, prec=prec).c()
+        assert lib.vqmc_local_energy_method(ct.byref(mm), ct.byref(meth)) == 0 and meth.value == want
+    forced = V.Model(24, 32, 9, prec=V.PREC_BF16X3, eloc=V.ELOC_LIGHTCONE).c()
+    assert lib.vqmc_local_energy_method(ct.byref(forced), ct.byref(meth)) == 1
+    assert lib.vqmc_local_energy_workspace(ct.byref(forced), 64, ct.byref(n)) == 1
+    # 16 x 16 fits every depth in every form
+    deep16 = V.Model(16, 32, 16, prec=V.PREC_BF16X3, eloc=V.ELOC_LIGHTCONE).c()
+    assert lib.vqmc_local_energy_method(ct.byref(deep16), ct.byref(meth)) == 0 and meth.value == V.ELOC_LIGHTCONE
     # dense: room for the packed weights of the 8 layers (36 KiB each), optional
     dense = V.Model(16, 32, 8, eloc=V.ELOC_DENSE).c()
     assert lib.vqmc_local_energy_workspace(ct.byref(dense), 64, ct.byref(n)) == 0 and n.value == 8 * 36864

@@ -41,7 +41,10 @@ def _check(gm, rm, th, s, tol_mean, tol_each=None):
 TOL = {V.PREC_FP32: (1e-5, 1e-4), V.PREC_BF16X3: (1e-4, 1e-3)}
 
 
-@pytest.mark.parametrize("L,C,n,B", [(6, 16, 2, 9), (8, 16, 3, 7), (10, 16, 6, 12), (12, 32, 4, 5)])
+# the last two use the twelve-wave shapes (2 and 3 row tiles per wave) with an
+# odd depth, where the next configuration's lift waits for a barrier of its own
+@pytest.mark.parametrize("L,C,n,B", [(6, 16, 2, 9), (8, 16, 3, 7), (10, 16, 6, 12), (12, 32, 4, 5),
+                                     (14, 32, 5, 2), (18, 16, 3, 3)])
 @pytest.mark.parametrize("prec", [V.PREC_FP32, V.PREC_BF16X3])
 def test_lightcone_parity(L, C, n, B, prec):
     gm, rm = _lc(L, C, n, prec)

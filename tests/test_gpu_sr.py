@@ -22,9 +22,13 @@ def _rel(a, b):
 
 
 # sizes span partial 64-blocks, odd orders (unaligned rows, scalar loads),
-# several 256-column outer panels, an order that is a multiple of 128 (the
-# right-hand side row then opens a block row of its own) and of 256
-CASES = [(300, 200), (200, 517), (64, 64), (97, 1), (130, 384), (256, 512), (515, 300), (777, 1030)]
+# several 512-column outer panels (above 1024 the trailing update of the
+# later columns runs on the side stream), an order that is a multiple of 128
+# (the right-hand side row then opens a block row of its own) and of 256, and
+# last outer panels of several sub-panels ending in a partial one (700, 1700:
+# the fused per-sub-panel launch with fewer than 64 columns)
+CASES = [(300, 200), (200, 517), (64, 64), (97, 1), (130, 384), (256, 512), (515, 300), (777, 1030),
+         (300, 700), (900, 1700)]
 
 
 @pytest.mark.parametrize("B,P", CASES)
