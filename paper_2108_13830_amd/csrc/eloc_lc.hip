@@ -81,23 +81,28 @@ __device__ __forceinline__ float exp2x(float a) { return __expf(2.f * fminf(fmax
 // tanh(a + b) - tanh(a) from E_a = e^{2a}, with the relative accuracy of b.
 // With E_c = E_a e^{2b}:
 //   tanh(a + b) - tanh(a) = 2 (E_c - E_a) / ((E_c + 1)(E_a + 1)),
-// where E_c - E_a = E_a (e^{2b} - 1) is taken from the series of e^x - 1
-// (six terms) when |2b| < 0.25 (truncation below 5e-8 relative) and as the
-// plain difference otherwise (the two then differ by a factor e^{0.25} or
-// more, so the difference loses at most a factor 4.5 in relative accuracy).
-// E_c is capped at 1e30: beyond it tanh(a + b) = 1 in FP32.  Where the
+// where E_c - E_a = 2 E_a sinh(b) e^b is taken as 2 E_a s(b), s(b) =
+// (e^{2b} - 1) / 2 from its series (six terms, truncation below 5e-8
+// relative) when |b| < 0.125, and as the plain difference otherwise (the two
+// then differ by a factor e^{0.25} or more, so the difference loses at most a
+// factor 4.5 in relative accuracy).  E_c is formed as the product E_a e^{2b}
+// (never as E_a + (E_c - E_a), which cancels when e^{2b} rounds against 1)
+// and capped at 1e30: beyond it tanh(a + b) = 1 in FP32.  Where the
 // denominator overflows (E_a > 3e8 with E_c capped) the result is 0, within
-// 1e-8 of the exact 2 / (E_a + 1).  One exponential and one reciprocal.
+// 1e-8 of the exact 2 / (E_a + 1).  One exponential (the hardware 2^x of
+// 2b log2 e) and one reciprocal.
 __device__ __forceinline__ float tanh_diff(float ea, float b) {
-  const float x = 2.f * b;
-  const float ec = fminf(ea * __expf(fminf(x, 88.f)), 1e30f);
-  const float em1 =
-      x * (1.f + x * (1.f / 2.f + x * (1.f / 6.f + x * (1.f / 24.f + x * (1.f / 120.f + x * (1.f / 720.f))))));
-  // both candidates are formed and one is picked bitwise (no branch)
-  const int sel = -(int)(fabsf(x) < 0.25f);
-  const int u = __float_as_int(ea * em1), t = __float_as_int(ec - ea);
+  const float e = __builtin_amdgcn_exp2f(fminf(b * 2.8853900817779268f, 126.f));
+  const float ec = fminf(ea * e, 1e30f);
+  const float sb =
+      b * (1.f + b * (1.f + b * (2.f / 3.f + b * (1.f / 3.f + b * (2.f / 15.f + b * (2.f / 45.f))))));
+  // both candidates are formed and one is picked bitwise (a conditional
+  // expression here compiles to a branch per element)
+  const int sel = -(int)(fabsf(b) < 0.125f);
+  const int u = __float_as_int(2.f * ea * sb), t = __float_as_int(ec - ea);
   const float num = __int_as_float(t ^ ((t ^ u) & sel));
-  return 2.f * num * __builtin_amdgcn_rcpf((ec + 1.f) * (ea + 1.f));
+  const float ea1 = ea + 1.f;
+  return 2.f * num * __builtin_amdgcn_rcpf(fmaf(ec, ea1, ea1));
 }
 
 // Unwrapped bounding box of the exchanged pair of bond k: rows y0..y0+ey,
