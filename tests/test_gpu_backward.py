@@ -99,3 +99,31 @@ def test_autograd_function_matches_oracle():
     ref = R.log_derivs(rm, th, s).T @ w
     np.testing.assert_allclose(host(t.grad), ref, rtol=1e-4, atol=1e-5 * np.abs(ref).max())
     np.testing.assert_allclose(host(lp), R.log_psi(rm, th, s)[0], atol=2e-4)
+
+
+def test_largest_model_log_psi_and_log_derivs():
+    """The largest model the library accepts (24x24, C = 32, n = 16 layers):
+    log|psi| in every precision and O_k (FP32) against the oracle on two
+    samples.  The log|psi| bars are those of the 10x10 parity test scaled by
+    sqrt(N C n) (rounding errors of that many terms adding in quadrature)."""
+    L, C, n, B = 24, 32, 16, 2
+    th = init_theta(C, n, seed=4)
+    s = uniform_sz0(L, B, seed=5)
+    scale = np.sqrt((L * L * C * n) / (100 * 16 * 6))
+    for prec, tol in ((V.PREC_FP32, 2e-4), (V.PREC_BF16X3, 5e-3), (V.PREC_BF16, 5.0)):
+        gm, rm = models(L, C, n, prec)
+        ref, rsg = R.log_psi(rm, th, s)
+        announce("largest model log_psi", prec)
+        sign = torch.empty(B, dtype=torch.int8, device="cuda")
+        got = host(V.vqmc_log_psi(gm, to_dev(th), to_dev(s), sign=sign))
+        err = np.abs(got - ref).max()
+        print("largest model prec=%d log_psi max|err| %.3e (bar %.3e)" % (prec, err, tol * scale))
+        assert err <= tol * scale
+        assert (host(sign) == rsg).all()
+    gm, rm = models(L, C, n)
+    announce("largest model log_derivs")
+    O = host(V.vqmc_log_derivs(gm, to_dev(th), to_dev(s)))
+    ref = R.log_derivs(rm, th, s)
+    rel = _rel_fro(O, ref)
+    print("largest model O rel fro %.3e" % rel)
+    assert rel <= 1e-4
