@@ -521,7 +521,7 @@ __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restric
 // y_K has already received the blocks after K.  Sub-blocks from the last:
 // t = y_s - L[>s][s]^T x[>s], x_s = Linv_s^T t.  One workgroup; every load
 // batch is unconditional (clamped indices) so that it is issued at once.
-__global__ __launch_bounds__(256) void chol_bwd_block_kernel(const double *__restrict__ M, int64_t n, int64_t ld,
+__global__ __launch_bounds__(256) void chol_bwd_block_kernel(const double *__restrict__ M, int64_t ld,
                                                             int64_t o, int mb, const double *__restrict__ Linv,
                                                             const double *__restrict__ y, double *__restrict__ x) {
   __shared__ double sx[SB];
@@ -695,7 +695,7 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
   double *y = M + n * ld;
   for (int64_t o = ((n - 1) / SB) * SB; o >= 0; o -= SB) {
     const int mb = (int)((n - o) < SB ? (n - o) : SB);
-    chol_bwd_block_kernel<<<1, 256, 0, st>>>(M, n, ld, o, mb, Linv, y, x);
+    chol_bwd_block_kernel<<<1, 256, 0, st>>>(M, ld, o, mb, Linv, y, x);
     if (o > 0) chol_bwd_update_kernel<<<(unsigned)((o + CB - 1) / CB), 256, 0, st>>>(M, ld, o, mb, x, y);
   }
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;

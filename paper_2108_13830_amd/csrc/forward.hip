@@ -292,7 +292,7 @@ __global__ __launch_bounds__(NW * 64, C <= 16 ? (TPW <= 7 ? 3 : 2) : 1) void elo
 // with its four rotations, at most G of them per forward pass.
 template <int C, int PREC, int NW, int TPW>
 __global__ __launch_bounds__(NW * 64) void sample_kernel(const float *__restrict__ theta,
-                                                         int8_t *__restrict__ spins, int B, int L,
+                                                         int8_t *__restrict__ spins, int L,
                                                          int n_layers, int n_sweeps, uint64_t seed,
                                                          uint64_t counter_base, int proposal, int R,
                                                          int G, double *__restrict__ log_psi,
@@ -507,12 +507,12 @@ static vqmc_status launch(Kind kind, const FwdArgs &a) {
     // the small engine (one wavefront) when all R evaluations fit one batch
     if (a.R * N <= ES::MAXROWS) {
       sample_kernel<C, PREC, I::SNW, I::STPW><<<a.B, I::SNW * 64, 0, a.stream>>>(
-          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
+          a.theta, a.spins_io, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
           a.R, a.out_d, a.out_i);
     } else {
       const int G = min(a.R, E::MAXROWS / N);
       sample_kernel<C, PREC, I::NW, I::TPW><<<a.B, I::NW * 64, 0, a.stream>>>(
-          a.theta, a.spins_io, a.B, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
+          a.theta, a.spins_io, a.L, a.n_layers, a.n_sweeps, a.seed, a.counter_base, a.proposal, a.R,
           G, a.out_d, a.out_i);
     }
     VQMC_LAUNCH_CHECK();
