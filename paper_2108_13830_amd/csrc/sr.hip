@@ -42,7 +42,10 @@ __device__ __forceinline__ double block_sum_t(double v, double *tmp) {
 }
 
 // scalar slots in the workspace
-enum { S_MEAN = 0, S_VAR, S_SUMEC, S_RR, S_NORMF, S_DONE, S_ITERS, S_REL, S_OBP, S_NSLOT = 16 };
+// scal slots; S_RRP + (it & 1): r.r entering CG iteration it (two slots, so
+// that the kernel forming the next value never overwrites one its other
+// workgroups still read)
+enum { S_MEAN = 0, S_VAR, S_SUMEC, S_RR, S_NORMF, S_DONE, S_ITERS, S_REL, S_OBP, S_RRP, S_RRP1, S_NSLOT = 16 };
 
 // ------------------------------------------------------------ reductions
 
@@ -385,6 +388,7 @@ __global__ __launch_bounds__(1024) void cg_init_kernel(const double *__restrict_
   const double obp = block_sum_t<1024>(op, tmp);
   if (threadIdx.x == 0) {
     scal[S_RR] = rr;
+    scal[S_RRP] = rr;
     scal[S_NORMF] = sqrt(rr);
     scal[S_DONE] = rr > 0.0 ? 0.0 : 1.0;
     scal[S_ITERS] = 0.0;
@@ -460,36 +464,72 @@ __global__ __launch_bounds__(256) void cg_apply_kernel(const double *__restrict_
   if (threadIdx.x == 0) pq_part[blockIdx.x] = v;
 }
 
-// alpha = rr / p.q; x += alpha p; r -= alpha q; beta = rr'/rr; p = r + beta p;
-// and <O>.p for the next matrix-vector product.
-__global__ __launch_bounds__(1024) void cg_step_kernel(int64_t P, double *__restrict__ x, double *__restrict__ r,
-                                                       double *__restrict__ p, const double *__restrict__ q,
-                                                       const double *__restrict__ obar,
-                                                       const double *__restrict__ pq_part, int npq,
-                                                       double *__restrict__ scal, double tol) {
-  __shared__ double tmp[16];
+// Sum of the n partials part[0..n) in a fixed order (every workgroup that
+// calls it gets the same value): strided per thread, then the block tree.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double *__restrict__ part, int n, double *tmp) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) v += part[i];
+  return block_sum_t<NT>(v, tmp);
+}
+
+// CG iteration it, after q = (S + eps I) p: alpha = rr / p.q; x += alpha p;
+// r -= alpha q; per-workgroup partial sums of r.r.
+__global__ __launch_bounds__(256) void cg_update_kernel(int64_t P, double *__restrict__ x, double *__restrict__ r,
+                                                        const double *__restrict__ p,
+                                                        const double *__restrict__ q,
+                                                        const double *__restrict__ pq_part, int npq,
+                                                        double *__restrict__ rr_part,
+                                                        const double *__restrict__ scal, int it) {
+  __shared__ double tmp[4];
   if (scal[S_DONE] != 0.0) return;
-  double pq = 0.0;
-  for (int i = 0; i < npq; ++i) pq += pq_part[i];
-  const double rr = scal[S_RR];
-  const double alpha = rr / pq;
-  double s = 0.0;
-  for (int64_t k = threadIdx.x; k < P; k += 1024) {
+  const double pq = sum_partials<256>(pq_part, npq, tmp);
+  const double alpha = scal[S_RRP + (it & 1)] / pq;
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (k < P) {
     x[k] += alpha * p[k];
     const double rk = r[k] - alpha * q[k];
     r[k] = rk;
-    s += rk * rk;
+    v = rk * rk;
   }
-  const double rr1 = block_sum_t<1024>(s, tmp);
-  const double beta = rr1 / rr;
-  double op = 0.0;
-  for (int64_t k = threadIdx.x; k < P; k += 1024) {
+  v = block_sum_t<256>(v, tmp);
+  if (threadIdx.x == 0) rr_part[blockIdx.x] = v;
+}
+
+// beta = rr' / rr; p = r + beta p; per-workgroup partial sums of <O>.p.  The
+// first workgroup keeps rr' for the next iteration.
+__global__ __launch_bounds__(256) void cg_dir_kernel(int64_t P, const double *__restrict__ r,
+                                                     double *__restrict__ p, const double *__restrict__ obar,
+                                                     const double *__restrict__ rr_part, int npq,
+                                                     double *__restrict__ op_part, double *__restrict__ scal,
+                                                     int it) {
+  __shared__ double tmp[4];
+  if (scal[S_DONE] != 0.0) return;
+  const double rr1 = sum_partials<256>(rr_part, npq, tmp);
+  const double beta = rr1 / scal[S_RRP + (it & 1)];
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (k < P) {
     const double pk = r[k] + beta * p[k];
     p[k] = pk;
-    op += obar[k] * pk;
+    v = obar[k] * pk;
   }
-  const double obp = block_sum_t<1024>(op, tmp);
+  v = block_sum_t<256>(v, tmp);
   if (threadIdx.x == 0) {
+    op_part[blockIdx.x] = v;
+    if (blockIdx.x == 0) scal[S_RRP + ((it + 1) & 1)] = rr1;
+  }
+}
+
+// <O>.p for the next matrix-vector product, the residual and the stopping test.
+__global__ __launch_bounds__(256) void cg_fin_kernel(const double *__restrict__ op_part, int npq,
+                                                     double *__restrict__ scal, int it, double tol) {
+  __shared__ double tmp[4];
+  if (scal[S_DONE] != 0.0) return;
+  const double obp = sum_partials<256>(op_part, npq, tmp);
+  if (threadIdx.x == 0) {
+    const double rr1 = scal[S_RRP + ((it + 1) & 1)];
     scal[S_RR] = rr1;
     scal[S_OBP] = obp;
     scal[S_ITERS] += 1.0;
@@ -516,7 +556,7 @@ struct SrPlan {
   int nch, rows_per_chunk;
   int npq;
   size_t off_scal, off_status, off_ec, off_obar, off_F, off_pa, off_pb, off_M, off_r, off_p, off_q,
-      off_u, off_pq, off_alpha, off_chol, total;
+      off_u, off_pq, off_rrp, off_opp, off_alpha, off_chol, total;
 };
 
 static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
@@ -558,6 +598,8 @@ static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
     s.off_q = take((size_t)P * 8);
     s.off_u = take((size_t)B * 8);
     s.off_pq = take((size_t)s.npq * 8);
+    s.off_rrp = take((size_t)s.npq * 8);
+    s.off_opp = take((size_t)s.npq * 8);
   } else {
     s.off_M = take((size_t)(B + 1) * ld_even(B) * 8);
     s.off_alpha = take((size_t)B * 8);
@@ -656,6 +698,8 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     double *q = reinterpret_cast<double *>(ws + pl.off_q);
     double *u = reinterpret_cast<double *>(ws + pl.off_u);
     double *pq = reinterpret_cast<double *>(ws + pl.off_pq);
+    double *rrp = reinterpret_cast<double *>(ws + pl.off_rrp);
+    double *opp = reinterpret_cast<double *>(ws + pl.off_opp);
     constexpr int RB = 8;  // rows per workgroup of the row pass
     const unsigned rgrid = (unsigned)((B + RB - 1) / RB);
     cg_init_kernel<<<1, 1024, 0, st>>>(Fv, P, obar, delta, r, p, scal);
@@ -670,7 +714,9 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
                                                         nullptr, scal);
       }
       cg_apply_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(pa, pl.nch, P, B, o->eps, p, q, pq, scal);
-      cg_step_kernel<<<1, 1024, 0, st>>>(P, delta, r, p, q, obar, pq, pl.npq, scal, o->tol);
+      cg_update_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(P, delta, r, p, q, pq, pl.npq, rrp, scal, it);
+      cg_dir_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(P, r, p, obar, rrp, pl.npq, opp, scal, it);
+      cg_fin_kernel<<<1, 256, 0, st>>>(opp, pl.npq, scal, it, o->tol);
     }
     VQMC_LAUNCH_CHECK();
   }
