@@ -467,32 +467,22 @@ struct TrailLoader {
   }
 };
 
-// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = OB): 128 x 128
-// tiles of rows [p1, nr) and columns [p1, n) on or below the diagonal,
-// M[r][c] -= sum_{t in [p0,p1)} L[r][t] L[c][t].  Tile (bi, bj) counts block
-// rows and columns from p1.  ncb > 0: only the block columns bj < ncb (the
-// next outer panel), tile t = (t / ncb, t % ncb); ncb == 0: the lower
-// triangle of block rows and columns >= OB / 128 (the rest).
+// Trailing matrix after the outer panel [p0, p1) (p1 - p0 = OB) past the next
+// outer panel: 128 x 128 tiles of rows and columns from p1 + OB on or below
+// the diagonal, M[r][c] -= sum_{t in [p0,p1)} L[r][t] L[c][t].  Tile t is
+// (bi, bj) of that lower block triangle.
 __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restrict__ M, int64_t n, int64_t nr,
                                                             int64_t ld, int64_t p0, int64_t p1, int ntiles,
-                                                            int ncb, int nchunks) {
+                                                            int nchunks) {
   constexpr int KC = 16;
   __shared__ Panel<double, KC, false> sA, sB;
   using TT = Tile128<double>;
   int bi, bj;
-  const int t = xcd_contiguous(blockIdx.x, ntiles);
-  if (ncb > 0) {
-    bi = t / ncb;
-    bj = t - bi * ncb;
-  } else {
-    lower_block(t, bi, bj);
-    bi += OB / 128;
-    bj += OB / 128;
-  }
-  const int64_t r0 = p1 + (int64_t)bi * 128, c0 = p1 + (int64_t)bj * 128;
-  // tiles above the diagonal, and the extra block row of the augmented matrix
-  // past the last column (uniform per workgroup)
-  if (bj > bi || c0 >= n) return;
+  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
+  const int64_t r0 = p1 + OB + (int64_t)bi * 128, c0 = p1 + OB + (int64_t)bj * 128;
+  // the extra block row of the augmented matrix past the last column
+  // (uniform per workgroup)
+  if (c0 >= n) return;
   TrailLoader<KC> ldr{M, ld, nr, r0, c0, p0};
   TT::acc_t acc[4][4];
   TT::zero(acc);
@@ -513,6 +503,88 @@ __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restric
       for (int tn = 0; tn < 4; ++tn) {
         const int col = TT::col_of(tn);
         if (row < nr && c0 + col < n) rp[col] = cur[tn] - acc[tm][tn][r];
+      }
+    }
+}
+
+// The columns of the next outer panel, [p1, p1 + OB), in 64 x 64 tiles:
+// M[r][c] -= sum_{t in [p0, p1)} L[r][t] L[c][t] for rows r in [p1, nr) and
+// c <= r (diagonal tiles also write their strict upper part, which nothing
+// reads).  This update lies on the chain between two outer panels; with four
+// times as many workgroups as 128 x 128 tiles it fills the device also when
+// few rows remain.  Tile t = (t / ncb, t % ncb); K in chunks of 64 columns,
+// the next chunk loaded into registers while the matrix cores use the
+// current one.
+__global__ __launch_bounds__(256, 2) void chol_next_panel_kernel(double *__restrict__ M, int64_t n, int64_t nr,
+                                                               int64_t ld, int64_t p0, int64_t p1, int ncb) {
+  __shared__ double sX[CB][CB + 2];
+  __shared__ double sY[CB][CB + 2];
+  const int bi = (int)blockIdx.x / ncb, bj = (int)blockIdx.x - bi * ncb;
+  const int64_t r0 = p1 + (int64_t)bi * CB, c0 = p1 + (int64_t)bj * CB;
+  if (bj > bi || c0 >= n) return;  // uniform per workgroup
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  auto load = [&](f64x2 (&v)[8], int64_t rb, int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, j = idx & 31;
+      v[q] = *reinterpret_cast<const f64x2 *>(M + clamp_row(rb + r, nr) * ld + k0 + 2 * j);
+    }
+  };
+  auto store = [&](const f64x2 (&v)[8], double (*dst)[CB + 2]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + 256 * q, r = idx >> 5, j = idx & 31;
+      *reinterpret_cast<f64x2 *>(&dst[r][2 * j]) = v[q];
+    }
+  };
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+  f64x2 vr[8], vc[8];
+  load(vr, r0, p0);
+  load(vc, c0, p0);
+  for (int64_t k0 = p0; k0 < p1; k0 += CB) {
+    store(vr, sX);
+    store(vc, sY);
+    __syncthreads();
+    if (k0 + CB < p1) {
+      load(vr, r0, k0 + CB);
+      load(vc, c0, k0 + CB);
+    }
+#pragma unroll 4
+    for (int ks = 0; ks < CB / 4; ++ks) {
+      const int k = ks * 4 + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = sX[wm * 32 + t * 16 + (lane & 15)][k];
+        b[t] = sY[wn * 32 + t * 16 + (lane & 15)][k];
+      }
+#pragma unroll
+      for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 2; ++tn) acc[tm][tn] = mma64(a[tm], b[tn], acc[tm][tn]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < 2; ++tn) {
+      const int64_t col = c0 + wn * 32 + tn * 16 + (lane & 15);
+      double cur[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
+        cur[r] = M[clamp_row(row, nr) * ld + (col < n ? col : c0)];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
+        if (row < nr && col < n) M[row * ld + col] = cur[r] - acc[tm][tn][r];
       }
     }
 }
@@ -671,21 +743,20 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
         chol_trsm_kernel<false><<<(unsigned)((below + CB - 1) / CB), 256, 0, st>>>(M, nr, ld, cl, m, Li);
     }
     if (p1 >= n) break;
-    const int T = (int)((nr - p1 + 127) / 128);
-    const int ncb = T < OB / 128 ? T : OB / 128;  // block columns of the next outer panel
     // the next panel's columns must also have the previous rest update
     if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
-    chol_trailing_kernel<<<(unsigned)(T * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, T * ncb, ncb, OB / 16);
-    if (T > ncb) {
-      const int nt = (T - ncb) * (T - ncb + 1) / 2;
+    const int T64 = (int)((nr - p1 + CB - 1) / CB), ncb = T64 < OB / CB ? T64 : OB / CB;
+    chol_next_panel_kernel<<<(unsigned)(T64 * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, ncb);
+    if (nr - p1 > OB) {
+      const int T = (int)((nr - p1 - OB + 127) / 128), nt = T * (T + 1) / 2;
       if (sd) {
         if (hipEventRecord(sd->next, st) != hipSuccess || hipStreamWaitEvent(sd->s, sd->next, 0) != hipSuccess)
           return VQMC_ERR_DEVICE;
-        chol_trailing_kernel<<<(unsigned)nt, 256, 0, sd->s>>>(M, n, nr, ld, p0, p1, nt, 0, OB / 16);
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, sd->s>>>(M, n, nr, ld, p0, p1, nt, OB / 16);
         if (hipEventRecord(sd->rest, sd->s) != hipSuccess) return VQMC_ERR_DEVICE;
         rest_pending = true;
       } else {
-        chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt, 0, OB / 16);
+        chol_trailing_kernel<<<(unsigned)nt, 256, 0, st>>>(M, n, nr, ld, p0, p1, nt, OB / 16);
       }
     }
   }
