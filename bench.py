@@ -241,7 +241,7 @@ def main():
     ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual,sym",
                     help="extra forms timed on the same inputs (comma list, or 'none')")
     ap.add_argument("--also", default="24x24",
-                    help="another workload timed after the main one (one step per form, bf16x3 and fp32), "
+                    help="another workload timed after the main one (one step per form, bf16x3, bf16 and fp32), "
                          "or 'none'")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel that scales HBM byte counters, then exit")
@@ -402,7 +402,7 @@ def main():
     if args.also != "none" and args.also != args.workload:
         del O, ws_o, ws_sr, ws_e
         torch.cuda.empty_cache()
-        out["also"] = other_workload(V, torch, args.also, ["bf16x3", "fp32"])
+        out["also"] = other_workload(V, torch, args.also, ["bf16x3", "bf16", "fp32"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, th_np, spins_np, min(args.cpu_sample, B))
     print(json.dumps(out), flush=True)

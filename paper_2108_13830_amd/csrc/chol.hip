@@ -329,20 +329,34 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double *__restrict__ M, 
       *reinterpret_cast<f64x2 *>(&sY[r][2 * j]) = vc;
     }
     __syncthreads();
+    if (blockIdx.x == 0) {
+      // R = C here, and M[C] holds what side_in holds: L0[C] = L0[R]
 #pragma unroll 4
-    for (int ks = 0; ks < KH / 4; ++ks) {
-      const int k = ks * 4 + (lane >> 4);
-      const double ar = sX[wave * 16 + (lane & 15)][k];
-      const double ac = sY[wave * 16 + (lane & 15)][k];
+      for (int ks = 0; ks < KH / 4; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double ar = sX[wave * 16 + (lane & 15)][k];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double l = sX[q * 16 + (lane & 15)][KH + 2 + k];
-        aR[q] = mma64(ar, l, aR[q]);
-        aC[q] = mma64(ac, l, aC[q]);
+        for (int q = 0; q < 4; ++q) aR[q] = mma64(ar, sX[q * 16 + (lane & 15)][KH + 2 + k], aR[q]);
+      }
+    } else {
+#pragma unroll 4
+      for (int ks = 0; ks < KH / 4; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const double ar = sX[wave * 16 + (lane & 15)][k];
+        const double ac = sY[wave * 16 + (lane & 15)][k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double l = sX[q * 16 + (lane & 15)][KH + 2 + k];
+          aR[q] = mma64(ar, l, aR[q]);
+          aC[q] = mma64(ac, l, aC[q]);
+        }
       }
     }
     __syncthreads();
   }
+  if (blockIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) aC[q] = aR[q];
   // L0[R] to M and to sX, L0[C] to sY (row-major [row][k], k in the c0 block)
 #pragma unroll
   for (int q = 0; q < 4; ++q)
