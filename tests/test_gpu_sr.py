@@ -26,9 +26,11 @@ def _rel(a, b):
 # later columns runs on the side stream), an order that is a multiple of 128
 # (the right-hand side row then opens a block row of its own) and of 256, and
 # last outer panels of several sub-panels ending in a partial one (700, 1700:
-# the fused per-sub-panel launch with fewer than 64 columns)
+# the fused per-sub-panel launch with fewer than 64 columns), and the next-panel
+# update's 64-row tiles ending in a partial tile (577: 66 rows after the first
+# panel) or exactly (1088: 577 rows, the rest of the trailing matrix one tile)
 CASES = [(300, 200), (200, 517), (64, 64), (97, 1), (130, 384), (256, 512), (515, 300), (777, 1030),
-         (300, 700), (900, 1700)]
+         (300, 700), (900, 1700), (300, 577), (640, 1088)]
 
 
 @pytest.mark.parametrize("B,P", CASES)
