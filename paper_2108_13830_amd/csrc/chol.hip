@@ -97,10 +97,20 @@ __device__ __forceinline__ void diag_factor(double *__restrict__ M, int64_t n, i
   double dcol[4] = {1.0, 1.0, 1.0, 1.0};
   bool bad = false;
   double rlo[4], rhi[4], cf[4];
-  // one step, with column B1 = (j+1) % 4 of this thread's block done first
-  auto step = [&](int j, auto b1c) {
-    constexpr int B1 = decltype(b1c)::value;
-    const double *v = colbuf[j & 1];
+  // Steps go in groups of four pivots j = 4g + t.  Whether row x0 + a lies
+  // at or above pivot j and whether column y0 + a lies past it depend, within
+  // a group, only on how bx and by compare with g and on a against t, so the
+  // masks of the update are 0/1 factors set once per group and picked at
+  // compile time: m_le / m_lt = [bx <= g] / [bx < g], c_ge / c_gt likewise
+  // for by; rows of upper blocks take the upper coefficient (x <= j only),
+  // rows of lower blocks the lower one (all rows), diagonal blocks by b <= a.
+  double m_le, m_lt, c_ge, c_gt, kA_le, kA_lt, kB_le, kB_lt;
+  bool xpiv;
+  // step j = 4g + t, with column B1 = (t + 1) % 4 of this thread's block done first
+  auto step = [&](int g, auto tc, auto b1c) {
+    constexpr int T = decltype(tc)::value, B1 = decltype(b1c)::value;
+    const int j = 4 * g + T;
+    const double *v = colbuf[T & 1];
     double vx[4], vy[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -112,25 +122,20 @@ __device__ __forceinline__ void diag_factor(double *__restrict__ M, int64_t n, i
       bad = true;
       d = 1.0;
     }
-    if (by == (j >> 2))
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if ((j & 3) == b) dcol[b] = d;
+    if (by == g) dcol[T] = d;
     const double q = recip(d);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int x = x0 + a;
-      const double rl = (x == j ? 1.0 : vx[a]) * q;
-      const double ru = x <= j ? rl : 0.0;
-      rlo[a] = upblk ? ru : rl;
-      rhi[a] = lowblk ? rl : ru;
-      cf[a] = (y0 + a > j) ? vy[a] : 0.0;
+      const double rl = (a == T && xpiv ? 1.0 : vx[a]) * q;
+      rlo[a] = rl * (a <= T ? kA_le : kA_lt);
+      rhi[a] = rl * (a <= T ? kB_le : kB_lt);
+      cf[a] = vy[a] * (a > T ? c_ge : c_gt);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) z[a][B1] -= (B1 <= a ? rlo[a] : rhi[a]) * cf[B1];
-    if (j + 1 < CB && by == ((j + 1) >> 2))
+    if (T < 3 ? by == g : (g + 1 < CB / 4 && by == g + 1))
 #pragma unroll
-      for (int a = 0; a < 4; ++a) colbuf[(j + 1) & 1][x0 + a] = z[a][B1];
+      for (int a = 0; a < 4; ++a) colbuf[(T + 1) & 1][x0 + a] = z[a][B1];
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -138,11 +143,20 @@ __device__ __forceinline__ void diag_factor(double *__restrict__ M, int64_t n, i
       for (int b = 0; b < 4; ++b)
         if (b != B1) z[a][b] -= (b <= a ? rlo[a] : rhi[a]) * cf[b];
   };
-  for (int j = 0; j < CB; j += 4) {
-    step(j, std::integral_constant<int, 1>{});
-    step(j + 1, std::integral_constant<int, 2>{});
-    step(j + 2, std::integral_constant<int, 3>{});
-    step(j + 3, std::integral_constant<int, 0>{});
+  for (int g = 0; g < CB / 4; ++g) {
+    m_le = bx <= g ? 1.0 : 0.0;
+    m_lt = bx < g ? 1.0 : 0.0;
+    c_ge = by >= g ? 1.0 : 0.0;
+    c_gt = by > g ? 1.0 : 0.0;
+    kA_le = upblk ? m_le : 1.0;
+    kA_lt = upblk ? m_lt : 1.0;
+    kB_le = lowblk ? 1.0 : m_le;
+    kB_lt = lowblk ? 1.0 : m_lt;
+    xpiv = bx == g;
+    step(g, std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
+    step(g, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
+    step(g, std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+    step(g, std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{});
   }
   if (bad && tid == 0) *status = 1;
 #pragma unroll
