@@ -532,6 +532,7 @@ struct Engine {
 
   // Writes tanh(acc + bias) of the wave's tiles into the activation buffer
   // (and, when scratch != nullptr, into scratch[row][co] in global memory).
+  template <bool ACT = true>
   __device__ static __forceinline__ void write_tiles(const f32x4 (&acc)[TPW][NT], const float *bias,
                                                      int R, char *act, float *scratch) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -546,7 +547,7 @@ struct Engine {
         for (int j = 0; j < 4; ++j) {
           const int row = T * 16 + (lane >> 4) * 4 + j;
           if (row < R && co < C) {
-            const float h = tanh_f(acc[i][nt][j] + bv);
+            const float h = ACT ? tanh_f(acc[i][nt][j] + bv) : acc[i][nt][j];
             store_act(act, row, co, h);
             if (scratch) scratch[row * C + co] = h;
           }
@@ -557,6 +558,7 @@ struct Engine {
 
   // write_tiles for transposed tiles (TR above): tanh(acc + bias) of four
   // consecutive channels per lane and row, one wide store each.
+  template <bool ACT = true>
   __device__ static __forceinline__ void write_tiles_t(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
                                                        char *act) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -573,7 +575,7 @@ struct Engine {
           if (row < R) {
             float h[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) h[j] = tanh_f(acc[i][nt][j] + bv[j]);
+            for (int j = 0; j < 4; ++j) h[j] = ACT ? tanh_f(acc[i][nt][j] + bv[j]) : acc[i][nt][j];
             store_act4(act, row, co0, h);
           }
         }
@@ -582,6 +584,7 @@ struct Engine {
   }
 
   // head_vals for transposed tiles.
+  template <bool ACT = true>
   __device__ static __forceinline__ void head_vals_t(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
                                                      float *hv) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -598,7 +601,7 @@ struct Engine {
           if (row < R) {
             f32x4 h;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) h[j] = tanh_f(acc[i][nt][j] + bv[j]);
+            for (int j = 0; j < 4; ++j) h[j] = ACT ? tanh_f(acc[i][nt][j] + bv[j]) : acc[i][nt][j];
             *reinterpret_cast<f32x4 *>(hv + row * C + co0) = h;
           }
         }
@@ -608,6 +611,7 @@ struct Engine {
 
   // The last layer's outputs tanh(acc + bias) as floats hv[row][C] (the
   // activation buffer, free once every wave has finished the layer's K loop).
+  template <bool ACT = true>
   __device__ static __forceinline__ void head_vals(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
                                                    float *hv) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -620,7 +624,7 @@ struct Engine {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int row = (wave + i * NW) * 16 + (lane >> 4) * 4 + j;
-          if (row < R && co < C) hv[row * C + co] = tanh_f(acc[i][nt][j] + bv);
+          if (row < R && co < C) hv[row * C + co] = ACT ? tanh_f(acc[i][nt][j] + bv) : acc[i][nt][j];
         }
       }
     }
@@ -641,10 +645,29 @@ struct Engine {
   // matrix work at these channel counts; FP32 keeps the row-major tiles,
   // which measured faster there (scalar stores either way).
   static constexpr bool FWD_TR = !F32;
+  template <bool ACT = true>
   __device__ static __forceinline__ void write_fwd(const f32x4 (&acc)[TPW][NT], const float *bias, int R,
                                                    char *act) {
-    if constexpr (FWD_TR) write_tiles_t(acc, bias, R, act);
-    else write_tiles(acc, bias, R, act, nullptr);
+    if constexpr (FWD_TR) write_tiles_t<ACT>(acc, bias, R, act);
+    else write_tiles<ACT>(acc, bias, R, act, nullptr);
+  }
+
+  // tanh(acc + bias) in place, in the forward pass's tile orientation
+  __device__ static __forceinline__ void act_tanh(f32x4 (&acc)[TPW][NT], const float *bias) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      float bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int co = FWD_TR ? nt * 16 + 4 * (lane >> 4) + j : nt * 16 + (lane & 15);
+        bv[j] = co < C ? bias[co] : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][nt][j] = tanh_f(acc[i][nt][j] + bv[j]);
+    }
   }
   __device__ static __forceinline__ void forward(const float *__restrict__ theta, int n_layers, const int8_t *sp,
                                                  int G, int N, char *smem_act, char *smem_frag,
@@ -660,21 +683,27 @@ struct Engine {
     for (int l = 1; l <= n_layers; ++l) {
       f32x4 acc[TPW][NT];
       kloop_tab<FWD_TR>(smem_act, smem_frag, nbt, acc);
-      __syncthreads();
       const float *bias = theta + layer_offset(C, l) + 9 * C * C;
+      // FP32: the activation is applied in registers before the barrier, so
+      // a wave that finishes its K loop early spends the wait on it and only
+      // the stores wait for the other waves' reads of this layer's input; the
+      // BF16 forms apply it after the barrier (their 448-row form has no
+      // registers to spare)
+      if constexpr (F32) act_tanh(acc, bias);
+      __syncthreads();
       if (l < n_layers) {
         if (dma) {
           stage_async<NTHR>(smem_frag, packed + (size_t)l * FRAG_LAYER, FRAG_LAYER);
-          write_fwd(acc, bias, R, smem_act);
+          write_fwd<!F32>(acc, bias, R, smem_act);
           wait_copies();
         } else {
-          write_fwd(acc, bias, R, smem_act);
+          write_fwd<!F32>(acc, bias, R, smem_act);
           stage_weights(theta + layer_offset(C, l + 1), smem_frag);
         }
       } else if constexpr (FWD_TR) {
-        head_vals_t(acc, bias, R, reinterpret_cast<float *>(smem_act));
+        head_vals_t<!F32>(acc, bias, R, reinterpret_cast<float *>(smem_act));
       } else {
-        head_vals(acc, bias, R, reinterpret_cast<float *>(smem_act));
+        head_vals<!F32>(acc, bias, R, reinterpret_cast<float *>(smem_act));
       }
       __syncthreads();
     }
