@@ -54,6 +54,22 @@ def test_sr_small_parity(B, P, method, s_prec):
         assert info["converged"] and info["rel_residual"] <= 1e-12
 
 
+@pytest.mark.parametrize("method,s_prec", [(V.SR_CHOLESKY, 0), (V.SR_CHOLESKY, 1), (V.SR_DUAL, 1), (V.SR_CG, 1)])
+def test_sr_run_to_run_bit_identical(method, s_prec):
+    """Two calls on the same inputs give the same bits: no atomics, fixed
+    reduction orders, and at this order (above 1024) the Cholesky's trailing
+    update runs on the side stream, ordered against the panel chain by events."""
+    B, P = 900, 1700
+    O, E = _rand(B, P, 5)
+    Od, Ed = to_dev(O), to_dev(E)
+    announce("sr determinism", method, s_prec)
+    opts = V.SrOpts(method=method, s_prec=s_prec, eps=1e-3, tol=1e-10, max_iter=300)
+    d1, F1, i1 = V.vqmc_sr_solve(Od, Ed, opts)
+    d2, F2, i2 = V.vqmc_sr_solve(Od, Ed, opts)
+    assert torch.equal(d1, d2) and torch.equal(F1, F2)
+    assert i1["iters"] == i2["iters"] and i1["rel_residual"] == i2["rel_residual"]
+
+
 def test_sr_fp32_s_is_reported_not_exact():
     B, P = 300, 200
     O, E = _rand(B, P, 11)
