@@ -542,9 +542,14 @@ __global__ __launch_bounds__(256, 2) void chol_trailing_kernel(double *__restric
 // times as many workgroups as 128 x 128 tiles it fills the device also when
 // few rows remain.  Tile t = (t / ncb, t % ncb); K in chunks of 64 columns,
 // the next chunk loaded into registers while the matrix cores use the
-// current one.
+// current one.  The workgroup of tile (0, 0), the next panel's first
+// diagonal block, then factors that block (inverse into Linv1), and the one of
+// tile (1, 0) copies its rows to side (nullable) for the next panel's first
+// step, as the panel's diagonal-block launch does for the first panel.
 __global__ __launch_bounds__(256, 2) void chol_next_panel_kernel(double *__restrict__ M, int64_t n, int64_t nr,
-                                                               int64_t ld, int64_t p0, int64_t p1, int ncb) {
+                                                               int64_t ld, int64_t p0, int64_t p1, int ncb,
+                                                               double *__restrict__ Linv1, int *__restrict__ status,
+                                                               double *__restrict__ side) {
   __shared__ double sX[CB][CB + 2];
   __shared__ double sY[CB][CB + 2];
   const int bi = (int)blockIdx.x / ncb, bj = (int)blockIdx.x - bi * ncb;
@@ -611,10 +616,18 @@ __global__ __launch_bounds__(256, 2) void chol_next_panel_kernel(double *__restr
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
-        if (row < nr && col < n) M[row * ld + col] = cur[r] - acc[tm][tn][r];
+        const int lr = wm * 32 + tm * 16 + (lane >> 4) + 4 * r;
+        const int64_t row = r0 + lr;
+        const double v = cur[r] - acc[tm][tn][r];
+        if (row < nr && col < n) M[row * ld + col] = v;
+        if (bi == 1 && bj == 0 && side) side[lr * CB + (int)(col - c0)] = v;
       }
     }
+  if (bi == 0 && bj == 0) {
+    // sX is free once the K loop is done
+    __syncthreads();
+    diag_factor(M, n, ld, p1, Linv1, status, reinterpret_cast<double (*)[CB]>(&sX[0][0]));
+  }
 }
 
 // Back substitution inside block o (mb <= 256 rows): L_KK^T x_K = y_K, where
@@ -750,8 +763,11 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
     // solving the previous sub-panel's rows and updating (left-looking inside
     // the panel) and factoring its own; last, the rows of the last sub-panel
     double *side = Linv + ((n + CB - 1) / CB) * CB * CB;
-    chol_diag_kernel<<<1, 256, 0, st>>>(M, n, ld, p0, Linv + (p0 / CB) * CB * CB, status,
-                                        p0 + CB < p1 ? side : nullptr);
+    // the first diagonal block of the later panels is factored by the update
+    // of the previous panel's trailing columns (below)
+    if (p0 == 0)
+      chol_diag_kernel<<<1, 256, 0, st>>>(M, n, ld, p0, Linv + (p0 / CB) * CB * CB, status,
+                                          p0 + CB < p1 ? side : nullptr);
     int64_t cl = p0;
     for (int64_t c1 = p0 + CB; c1 < p1; c1 += CB) {
       const int64_t c0 = c1 - CB, m1 = (n - c1) < CB ? (n - c1) : CB;
@@ -774,7 +790,9 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
     // the next panel's columns must also have the previous rest update
     if (rest_pending && hipStreamWaitEvent(st, sd->rest, 0) != hipSuccess) return VQMC_ERR_DEVICE;
     const int T64 = (int)((nr - p1 + CB - 1) / CB), ncb = T64 < OB / CB ? T64 : OB / CB;
-    chol_next_panel_kernel<<<(unsigned)(T64 * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, ncb);
+    chol_next_panel_kernel<<<(unsigned)(T64 * ncb), 256, 0, st>>>(M, n, nr, ld, p0, p1, ncb,
+                                                                  Linv + (p1 / CB) * CB * CB, status,
+                                                                  n - p1 > CB ? side : nullptr);
     if (nr - p1 > OB) {
       const int T = (int)((nr - p1 - OB + 127) / 128), nt = T * (T + 1) / 2;
       if (sd) {
