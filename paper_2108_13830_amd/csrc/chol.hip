@@ -13,7 +13,11 @@
 // left-looking update of its own columns and the factorisation of its own
 // diagonal block (by the workgroup that updated it), so that the chain of
 // dependent launches, which competes with the concurrent trailing update for
-// compute units, is one launch per 64 columns.
+// compute units, is one launch per 64 columns.  After an outer panel, the
+// update of the next panel's columns runs on the caller's stream (its first
+// tile's workgroup then factors the next panel's first diagonal block) and
+// the rest of the trailing update on a side stream, overlapping the next
+// panel's chain.
 //
 // The right-hand side rides along as an extra last row of the matrix: the
 // factorisation of [[M, r], [r^T, *]] leaves y = L^-1 r in that row, so the
