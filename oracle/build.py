@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libvqmc_ref.so")
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "vqmc_ref.c")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall",
            "-Wextra", "-Wno-unused-parameter", src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -53,22 +53,33 @@ static double forward(const vqmc_ref_model *m, const double *theta,
   const int L = m->L, N = L * L, C = m->C;
   double *prev = (double *)malloc(sizeof(double) * (size_t)C * N);
   double *cur = (double *)malloc(sizeof(double) * (size_t)C * N);
+  /* the layer's weights as wt[ky][kx][ci][co] and one site's outputs z[co]:
+   * the same sums as the formula above, taken tap by tap so that the
+   * innermost loop runs over independent outputs */
+  double *wt = (double *)malloc(sizeof(double) * (size_t)9 * C * C);
+  double *z = (double *)malloc(sizeof(double) * (size_t)C);
   for (int i = 0; i < N; ++i) prev[i] = (double)s[i];
   for (int l = 0; l <= m->n; ++l) {
     const int cin = (int)layer_cin(m, l);
     const double *W = theta + weight_offset(m, l);
     const double *bias = W + (int64_t)C * cin * 9;
     for (int co = 0; co < C; ++co)
-      for (int y = 0; y < L; ++y)
-        for (int x = 0; x < L; ++x) {
-          double z = bias[co];
-          for (int ci = 0; ci < cin; ++ci)
-            for (int ky = 0; ky < 3; ++ky)
-              for (int kx = 0; kx < 3; ++kx)
-                z += W[((co * cin + ci) * 3 + ky) * 3 + kx] *
-                     prev[ci * N + wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L)];
-          cur[co * N + y * L + x] = tanh(z);
-        }
+      for (int ci = 0; ci < cin; ++ci)
+        for (int t = 0; t < 9; ++t) wt[((size_t)t * cin + ci) * C + co] = W[(co * cin + ci) * 9 + t];
+    for (int y = 0; y < L; ++y)
+      for (int x = 0; x < L; ++x) {
+        for (int co = 0; co < C; ++co) z[co] = bias[co];
+        for (int ky = 0; ky < 3; ++ky)
+          for (int kx = 0; kx < 3; ++kx) {
+            const int src = wrap(y + ky - 1, L) * L + wrap(x + kx - 1, L);
+            const double *w = wt + (size_t)(ky * 3 + kx) * cin * C;
+            for (int ci = 0; ci < cin; ++ci) {
+              const double v = prev[ci * N + src];
+              for (int co = 0; co < C; ++co) z[co] += w[ci * C + co] * v;
+            }
+          }
+        for (int co = 0; co < C; ++co) cur[co * N + y * L + x] = tanh(z[co]);
+      }
     if (acts) memcpy(acts + (size_t)l * C * N, cur, sizeof(double) * (size_t)C * N);
     double *t = prev; prev = cur; cur = t;
   }
@@ -76,6 +87,8 @@ static double forward(const vqmc_ref_model *m, const double *theta,
   for (int i = 0; i < C * N; ++i) sum += prev[i];
   free(prev);
   free(cur);
+  free(wt);
+  free(z);
   return sum;
 }
 
