@@ -47,8 +47,10 @@ typedef enum {
   VQMC_ERR_DEVICE = 3,    /* a HIP call or a kernel launch failed          */
   VQMC_ERR_WORKSPACE = 4, /* workspace missing or smaller than required    */
   VQMC_ERR_NOT_SPD = 5,   /* Cholesky met a non-positive pivot             */
-  VQMC_WARN_NOT_CONVERGED = 6 /* CG reached max_iter; delta and info hold the
-                                 last iterate                              */
+  VQMC_WARN_NOT_CONVERGED = 6, /* CG reached max_iter; delta and info hold the
+                                  last iterate                             */
+  VQMC_ERR_NONFINITE = 7  /* the SR solve met non-finite energies, or a
+                             non-finite CG residual (non-finite O)         */
 } vqmc_status;
 
 /* Arithmetic of the convolutions (all accumulate in FP32):
@@ -221,7 +223,11 @@ vqmc_status vqmc_sr_workspace(int32_t B, int64_t P, const vqmc_sr_opts *o, size_
  *   delta solves (S + eps I) delta = F.
  * O: dev float [B][ldO]; e_loc: dev double [B]; delta: dev double [P];
  * F: dev double [P] (nullable); info: host (nullable, forces a stream
- * synchronisation).  B >= 2, P >= 1. */
+ * synchronisation).  B >= 2, P >= 1.  Only with info are the device-side
+ * failures returned: VQMC_ERR_NOT_SPD when the factorisation met a
+ * non-positive pivot (it then finishes with unit pivots, so delta is
+ * finite but wrong), VQMC_ERR_NONFINITE when the energies or the CG
+ * residual are not finite (CG then stops). */
 vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *e_loc,
                           int32_t B, int64_t P, const vqmc_sr_opts *o,
                           double *delta, double *F, void *workspace,
@@ -240,10 +246,13 @@ vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *e_loc,
  * e_loc (dev double [B], nullable) receives the local energies of the
  * sampled configurations (under the theta the call started with).  info
  * (host, nullable) receives their mean and variance and the SR report, and
- * forces a stream synchronisation; only then is a failed factorisation
- * (VQMC_ERR_NOT_SPD, theta left unchanged) detected.  With CG that reaches
- * max_iter the update uses the last iterate and VQMC_WARN_NOT_CONVERGED is
- * returned.  workspace: dev, vqmc_vmc_step_workspace bytes (E_s, O, delta
+ * forces a stream synchronisation.  The update kernel reads the SR solve's
+ * device status and leaves theta bit-unchanged when the factorisation met a
+ * non-positive pivot or the energies or CG residual were not finite, with or
+ * without info; only with info is that failure also returned
+ * (VQMC_ERR_NOT_SPD or VQMC_ERR_NONFINITE).  With CG that reaches max_iter
+ * the update uses the last iterate and VQMC_WARN_NOT_CONVERGED is returned
+ * (with info).  workspace: dev, vqmc_vmc_step_workspace bytes (E_s, O, delta
  * and the three inner workspaces).  B >= 2, n_sweeps >= 0. */
 vqmc_status vqmc_vmc_step(const vqmc_model *m, float *theta, int8_t *spins,
                           int32_t B, int32_t n_sweeps, uint64_t seed,

@@ -15,6 +15,7 @@ extern "C" const char *vqmc_status_string(vqmc_status s) {
     case VQMC_ERR_WORKSPACE: return "workspace missing or too small";
     case VQMC_ERR_NOT_SPD: return "matrix not positive definite";
     case VQMC_WARN_NOT_CONVERGED: return "conjugate gradients did not converge";
+    case VQMC_ERR_NONFINITE: return "non-finite energies or residual in the SR solve";
   }
   return "unknown status";
 }

@@ -28,6 +28,13 @@ inline bool model_valid(const vqmc_model *m) {
 
 inline int64_t num_params(int C, int n) { return (int64_t)10 * C + (int64_t)n * (9 * C * C + C); }
 
+// The SR solve's two device status words inside its workspace (the solve
+// clears both first): word 0 is set when the Cholesky factorisation meets a
+// non-positive pivot, word 1 when the energies or the CG residual are not
+// finite.  For options that pass sr_opts_valid.
+bool sr_opts_valid(const vqmc_sr_opts *o);
+int *sr_status_word(void *workspace, int32_t B, int64_t P, const vqmc_sr_opts *o);
+
 #define VQMC_LAUNCH_CHECK()                                   \
   do {                                                        \
     if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE; \

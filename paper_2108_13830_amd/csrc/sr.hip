@@ -71,6 +71,7 @@ __global__ __launch_bounds__(1024) void energy_stats_kernel(const double *__rest
     scal[S_MEAN] = mean;
     scal[S_VAR] = var;
     scal[S_SUMEC] = sc;
+    if (!isfinite(mean) || !isfinite(var)) status[1] = 1;
   }
 }
 
@@ -373,7 +374,8 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const float *__restrict__ 
 __global__ __launch_bounds__(1024) void cg_init_kernel(const double *__restrict__ F, int64_t P,
                                                        const double *__restrict__ obar,
                                                        double *__restrict__ x, double *__restrict__ r,
-                                                       double *__restrict__ p, double *__restrict__ scal) {
+                                                       double *__restrict__ p, double *__restrict__ scal,
+                                                       int *__restrict__ status) {
   __shared__ double tmp[16];
   double s = 0.0, op = 0.0;
   for (int64_t k = threadIdx.x; k < P; k += 1024) {
@@ -391,6 +393,11 @@ __global__ __launch_bounds__(1024) void cg_init_kernel(const double *__restrict_
     scal[S_RRP] = rr;
     scal[S_NORMF] = sqrt(rr);
     scal[S_DONE] = rr > 0.0 ? 0.0 : 1.0;
+    // a non-finite right-hand side (non-finite O or E) stops CG at once
+    if (!isfinite(rr)) {
+      status[1] = 1;
+      scal[S_DONE] = 1.0;
+    }
     scal[S_ITERS] = 0.0;
     scal[S_REL] = 0.0;
     scal[S_OBP] = obp;
@@ -524,7 +531,8 @@ __global__ __launch_bounds__(256) void cg_dir_kernel(int64_t P, const double *__
 
 // <O>.p for the next matrix-vector product, the residual and the stopping test.
 __global__ __launch_bounds__(256) void cg_fin_kernel(const double *__restrict__ op_part, int npq,
-                                                     double *__restrict__ scal, int it, double tol) {
+                                                     double *__restrict__ scal, int it, double tol,
+                                                     int *__restrict__ status) {
   __shared__ double tmp[4];
   if (scal[S_DONE] != 0.0) return;
   const double obp = sum_partials<256>(op_part, npq, tmp);
@@ -536,6 +544,10 @@ __global__ __launch_bounds__(256) void cg_fin_kernel(const double *__restrict__ 
     const double rel = sqrt(rr1) / scal[S_NORMF];
     scal[S_REL] = rel;
     if (rel <= tol) scal[S_DONE] = 1.0;
+    if (!isfinite(rel)) {
+      status[1] = 1;
+      scal[S_DONE] = 1.0;
+    }
   }
 }
 
@@ -609,9 +621,13 @@ static SrPlan make_plan(int B, int64_t P, const vqmc_sr_opts *o) {
   return s;
 }
 
-static bool opts_valid(const vqmc_sr_opts *o) {
+bool sr_opts_valid(const vqmc_sr_opts *o) {
   return o && o->method >= 0 && o->method <= 3 && (o->s_prec == 0 || o->s_prec == 1) && o->eps > 0.0 &&
          o->tol >= 0.0 && o->max_iter >= 0;
+}
+
+int *sr_status_word(void *workspace, int32_t B, int64_t P, const vqmc_sr_opts *o) {
+  return reinterpret_cast<int *>(reinterpret_cast<char *>(workspace) + make_plan(B, P, o).off_status);
 }
 
 }  // namespace vqmc
@@ -619,7 +635,7 @@ static bool opts_valid(const vqmc_sr_opts *o) {
 using namespace vqmc;
 
 extern "C" vqmc_status vqmc_sr_workspace(int32_t B, int64_t P, const vqmc_sr_opts *o, size_t *bytes) {
-  if (!opts_valid(o) || !bytes) return VQMC_ERR_ARG;
+  if (!sr_opts_valid(o) || !bytes) return VQMC_ERR_ARG;
   if (B < 2 || P < 1) return VQMC_ERR_SHAPE;
   *bytes = make_plan(B, P, o).total;
   return VQMC_OK;
@@ -628,7 +644,7 @@ extern "C" vqmc_status vqmc_sr_workspace(int32_t B, int64_t P, const vqmc_sr_opt
 extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *e_loc, int32_t B, int64_t P,
                                      const vqmc_sr_opts *o, double *delta, double *F, void *workspace,
                                      size_t ws_bytes, vqmc_sr_info *info, hipStream_t st) {
-  if (!opts_valid(o)) return VQMC_ERR_ARG;
+  if (!sr_opts_valid(o)) return VQMC_ERR_ARG;
   if (B < 2 || P < 1 || ldO < P) return VQMC_ERR_SHAPE;
   if (!O || !e_loc || !delta) return VQMC_ERR_ARG;
   const SrPlan pl = make_plan(B, P, o);
@@ -702,7 +718,7 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     double *opp = reinterpret_cast<double *>(ws + pl.off_opp);
     constexpr int RB = 8;  // rows per workgroup of the row pass
     const unsigned rgrid = (unsigned)((B + RB - 1) / RB);
-    cg_init_kernel<<<1, 1024, 0, st>>>(Fv, P, obar, delta, r, p, scal);
+    cg_init_kernel<<<1, 1024, 0, st>>>(Fv, P, obar, delta, r, p, scal, status);
     for (int it = 0; it < o->max_iter; ++it) {
       if (vec) {
         cg_rowdot_kernel<RB, true><<<rgrid, 256, 0, st>>>(O, ldO, B, P, p, u, scal);
@@ -716,7 +732,7 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
       cg_apply_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(pa, pl.nch, P, B, o->eps, p, q, pq, scal);
       cg_update_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(P, delta, r, p, q, pq, pl.npq, rrp, scal, it);
       cg_dir_kernel<<<(unsigned)pl.npq, 256, 0, st>>>(P, r, p, obar, rrp, pl.npq, opp, scal, it);
-      cg_fin_kernel<<<1, 256, 0, st>>>(opp, pl.npq, scal, it, o->tol);
+      cg_fin_kernel<<<1, 256, 0, st>>>(opp, pl.npq, scal, it, o->tol, status);
     }
     VQMC_LAUNCH_CHECK();
   }
@@ -732,6 +748,7 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     info->iters = pl.method == 2 ? (int32_t)h[S_ITERS] : 0;
     info->rel_residual = pl.method == 2 ? h[S_REL] : 0.0;
     if (hs[0]) return VQMC_ERR_NOT_SPD;
+    if (hs[1]) return VQMC_ERR_NONFINITE;
     if (pl.method == 2 && h[S_DONE] == 0.0) return VQMC_WARN_NOT_CONVERGED;
   }
   return VQMC_OK;

@@ -8,9 +8,12 @@
 
 namespace vqmc {
 
-// theta_k <- theta_k - lr * delta_k, in FP64, rounded once to FP32.
+// theta_k <- theta_k - lr * delta_k, in FP64, rounded once to FP32; nothing
+// is written when the SR solve flagged a non-positive pivot or non-finite
+// values (status words 0 and 1 of its workspace).
 __global__ void sr_update_kernel(float *__restrict__ theta, const double *__restrict__ delta, int64_t P,
-                                 double lr) {
+                                 double lr, const int *__restrict__ status) {
+  if (status[0] != 0 || status[1] != 0) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < P) theta[k] = (float)((double)theta[k] - lr * delta[k]);
 }
@@ -55,7 +58,7 @@ using namespace vqmc;
 
 extern "C" vqmc_status vqmc_vmc_step_workspace(const vqmc_model *m, int32_t B, const vqmc_sr_opts *sr,
                                                size_t *bytes) {
-  if (!model_valid(m) || !sr || !bytes) return VQMC_ERR_ARG;
+  if (!model_valid(m) || !sr_opts_valid(sr) || !bytes) return VQMC_ERR_ARG;
   if (B < 2) return VQMC_ERR_SHAPE;
   VmcPlan p{};
   const vqmc_status st = make_plan(m, B, sr, p);
@@ -68,7 +71,7 @@ extern "C" vqmc_status vqmc_vmc_step(const vqmc_model *m, float *theta, int8_t *
                                      int32_t n_sweeps, uint64_t seed, uint64_t counter_base, int32_t proposal,
                                      const vqmc_sr_opts *sr, double lr, double *e_loc, void *workspace,
                                      size_t ws_bytes, vqmc_sr_info *info, hipStream_t stream) {
-  if (!model_valid(m) || !sr) return VQMC_ERR_ARG;
+  if (!model_valid(m) || !sr_opts_valid(sr)) return VQMC_ERR_ARG;
   if (B < 2 || n_sweeps < 0) return VQMC_ERR_SHAPE;
   if (!theta || !spins || proposal < 0 || proposal > 1 || !(lr == lr)) return VQMC_ERR_ARG;
   VmcPlan p{};
@@ -91,7 +94,8 @@ extern "C" vqmc_status vqmc_vmc_step(const vqmc_model *m, float *theta, int8_t *
   const vqmc_status sr_st =
       vqmc_sr_solve(O, p.ldO, e, B, p.P, sr, delta, nullptr, w + p.off_ws, p.ws, info, stream);
   if (sr_st != VQMC_OK && sr_st != VQMC_WARN_NOT_CONVERGED) return sr_st;
-  sr_update_kernel<<<(unsigned)((p.P + 255) / 256), 256, 0, stream>>>(theta, delta, p.P, lr);
+  const int *status = sr_status_word(w + p.off_ws, B, p.P, sr);
+  sr_update_kernel<<<(unsigned)((p.P + 255) / 256), 256, 0, stream>>>(theta, delta, p.P, lr, status);
   VQMC_LAUNCH_CHECK();
   return sr_st;
 }

@@ -26,7 +26,7 @@ ELOC_AUTO, ELOC_DENSE, ELOC_LIGHTCONE = 0, 1, 2
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported size", 3: "device error",
           4: "workspace too small", 5: "matrix not positive definite",
-          6: "conjugate gradients did not converge"}
+          6: "conjugate gradients did not converge", 7: "non-finite energies or residual in the SR solve"}
 WARN_NOT_CONVERGED = 6
 
 

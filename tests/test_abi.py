@@ -44,7 +44,7 @@ def test_num_params_and_model_validation():
 
 def test_status_strings():
     lib = V.lib()
-    for code in range(7):
+    for code in range(8):
         assert lib.vqmc_status_string(code)
     assert lib.vqmc_status_string(99) == b"unknown status"
 

@@ -134,3 +134,44 @@ def test_vmc_step_argument_errors():
         V.vqmc_vmc_step(gm, th, s, 1, 0, 0, 0.1, workspace=torch.empty(1, dtype=torch.uint8, device="cuda"))
     with pytest.raises(V.VqmcError):
         V.vqmc_vmc_step(gm, th, s, 1, 0, 0, 0.1, proposal=3)
+
+
+@pytest.mark.parametrize("method", [V.SR_CHOLESKY, V.SR_DUAL, V.SR_CG])
+def test_vmc_step_leaves_theta_unchanged_on_failed_solve(method):
+    """A non-finite parameter makes every energy and log-derivative
+    non-finite: the Cholesky meets a non-positive (NaN) pivot, CG a
+    non-finite residual.  With or without info, theta must come back bit for
+    bit unchanged, and with info the call reports the failure."""
+    L, C, n, B = 6, 8, 2, 64
+    gm, _ = models(L, C, n)
+    th_np = init_theta(C, n, seed=0)
+    th_np[3] = np.nan
+    opts = V.SrOpts(method=method, s_prec=1, eps=1e-4, tol=1e-8, max_iter=20)
+    announce("vmc step with a NaN parameter", method)
+    for want_info in (False, True):
+        th = to_dev(th_np)
+        s = to_dev(neel(L, B))
+        before = host(th).view(np.int32).copy()
+        if want_info:
+            with pytest.raises(V.VqmcError) as err:
+                V.vqmc_vmc_step(gm, th, s, 1, 3, 0, 0.1, opts=opts, want_info=True)
+            assert err.value.status in (5, 7)
+        else:
+            V.vqmc_vmc_step(gm, th, s, 1, 3, 0, 0.1, opts=opts, want_info=False)
+        assert np.array_equal(host(th).view(np.int32), before)
+
+
+def test_sr_solve_reports_non_finite_energies():
+    """A NaN energy: the solve returns VQMC_ERR_NONFINITE with info, for the
+    exact forms and for CG (which stops at once instead of reporting a
+    converged zero step)."""
+    rng = np.random.default_rng(0)
+    O = to_dev(rng.standard_normal((64, 40)).astype(np.float32))
+    e_np = rng.standard_normal(64)
+    e_np[7] = np.nan
+    e = to_dev(e_np)
+    for method in (V.SR_CHOLESKY, V.SR_DUAL, V.SR_CG):
+        announce("sr solve with a NaN energy", method)
+        with pytest.raises(V.VqmcError) as err:
+            V.vqmc_sr_solve(O, e, V.SrOpts(method=method, eps=1e-3))
+        assert err.value.status == 7
