@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libvqmc_ref.so")
 
 __all__ = [
     "RefModel", "lib", "num_params", "log_psi", "local_energy", "log_derivs",
-    "sr_solve", "sr_matrix", "philox4x32_10", "sample", "sz0_states",
+    "sr_solve", "sr_matrix", "sr_apply", "philox4x32_10", "sample", "sz0_states",
     "bond_pairs", "hamiltonian", "exact_energy", "ground_energy",
 ]
 
@@ -72,6 +72,7 @@ def lib():
         L.vqmc_ref_sr_solve.argtypes = [P, ct.c_int64, P, ct.c_int32, ct.c_int64, ct.c_double,
                                         ct.c_int32, P, P, P, P]
         L.vqmc_ref_sr_matrix.argtypes = [P, ct.c_int64, ct.c_int32, ct.c_int64, P]
+        L.vqmc_ref_sr_apply.argtypes = [P, ct.c_int64, ct.c_int32, ct.c_int64, P, ct.c_double, P, P]
         L.vqmc_ref_philox4x32_10.argtypes = [P, P, P]
         L.vqmc_ref_philox4x32_10.restype = None
         L.vqmc_ref_sample.argtypes = [ct.POINTER(_Model), P, P, ct.c_int32, ct.c_int32,
@@ -159,6 +160,19 @@ def sr_matrix(O) -> np.ndarray:
     rc = lib().vqmc_ref_sr_matrix(_p(O), P, B, P, _p(S))
     assert rc == 0, rc
     return S
+
+
+def sr_apply(O, mean, v, eps: float = 1e-4) -> np.ndarray:
+    """(S + eps I) v with S = (1/B) O^cT O^c applied matrix-free; the column
+    means of O are passed in."""
+    O = np.ascontiguousarray(np.asarray(O, dtype=np.float64))
+    mean = np.ascontiguousarray(np.asarray(mean, dtype=np.float64))
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    B, P = O.shape
+    out = np.zeros(P)
+    rc = lib().vqmc_ref_sr_apply(_p(O), P, B, P, _p(mean), eps, _p(v), _p(out))
+    assert rc == 0, rc
+    return out
 
 
 def philox4x32_10(ctr, key):

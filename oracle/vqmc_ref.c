@@ -391,6 +391,31 @@ static void chol_solve(const double *Lm, int64_t n, const double *r, double *x) 
   }
 }
 
+/* One application of the shifted SR matrix of Eq. (convar-matrix) to a
+ * vector, without forming it: out = (1/B) sum_b (O_b - <O>) ((O_b - <O>) . v)
+ * + eps v, with the column means <O> given (the work of one iteration of an
+ * iterative solve of Eq. delta).  Two passes over O: the row products u_b,
+ * then the columns summed over b in order. */
+int vqmc_ref_sr_apply(const double *O, int64_t ldO, int32_t B, int64_t P, const double *mean,
+                      double eps, const double *v, double *out) {
+  if (!O || !mean || !v || !out || B < 1 || P < 1 || ldO < P) return -1;
+  double *u = (double *)malloc(sizeof(double) * (size_t)B);
+#pragma omp parallel for schedule(static)
+  for (int b = 0; b < B; ++b) {
+    double s = 0.0;
+    for (int64_t k = 0; k < P; ++k) s += (O[(size_t)b * ldO + k] - mean[k]) * v[k];
+    u[b] = s;
+  }
+  for (int64_t k = 0; k < P; ++k) out[k] = 0.0;
+  for (int b = 0; b < B; ++b) {
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < P; ++k) out[k] += (O[(size_t)b * ldO + k] - mean[k]) * u[b];
+  }
+  for (int64_t k = 0; k < P; ++k) out[k] = out[k] / B + eps * v[k];
+  free(u);
+  return 0;
+}
+
 int vqmc_ref_sr_matrix(const double *O, int64_t ldO, int32_t B, int64_t P, double *S) {
   if (!O || !S || B < 1 || P < 1 || ldO < P) return -1;
   double *mean = (double *)malloc(sizeof(double) * (size_t)P);

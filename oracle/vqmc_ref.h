@@ -68,6 +68,11 @@ int vqmc_ref_sr_solve(const double *O, int64_t ldO, const double *e_loc,
                       double *delta, double *F, double *e_mean, double *e_var);
 
 /* S = <O O> - <O><O> written to S [P][P] (for tests at small P). */
+/* out = (S + eps I) v with S of Eq. (convar-matrix) applied without
+ * forming it; mean: the column means <O> [P]. */
+int vqmc_ref_sr_apply(const double *O, int64_t ldO, int32_t B, int64_t P, const double *mean,
+                      double eps, const double *v, double *out);
+
 int vqmc_ref_sr_matrix(const double *O, int64_t ldO, int32_t B, int64_t P,
                        double *S);
 

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+from sampler_stats import check_histogram
 from gpu_common import R, V, models, to_dev, host, announce
 from vqmc_inputs import init_theta, neel, uniform_sz0, ferro_like_sz0
 
@@ -252,11 +253,12 @@ def test_sampler_distribution_4x4():
     el = R.local_energy(rm, th, states)
     p = np.exp(2 * (la - la.max()))
     p /= p.sum()
-    chains = 4096
+    chains = 16384
     sd = to_dev(neel(4, chains))
     announce("sampler distribution")
     V.vqmc_sample(gm, to_dev(th), sd, n_sweeps=80, seed=2024)
     s = host(sd)
+    print(check_histogram(s, states, p))
     ms = _stag(states, 4)
     hist = np.bincount(_stag(s, 4), minlength=9)[:9]
     exp = np.array([p[ms == k].sum() for k in range(9)]) * chains

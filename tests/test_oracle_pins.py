@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle as R
+from sampler_stats import check_histogram
 from vqmc_inputs import init_theta, neel, uniform_sz0, ferro_like_sz0
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -310,6 +311,10 @@ def test_sr_against_numpy_cov_and_solve():
         np.testing.assert_allclose(r1["delta"], d, rtol=1e-9, atol=1e-11)
         assert r0["e_mean"] == pytest.approx(E.mean(), rel=1e-14)
         assert r0["e_var"] == pytest.approx(E.var(), rel=1e-12)
+        # the matrix-free application (S + eps I) v against numpy's covariance
+        v = np.random.default_rng(B + P).standard_normal(P)
+        np.testing.assert_allclose(R.sr_apply(O, O.mean(axis=0), v, eps), (S + eps * np.eye(P)) @ v,
+                                   rtol=1e-12, atol=1e-13)
 
 
 def test_sr_special_cases():
@@ -375,18 +380,27 @@ def _stag(states, L):
 
 @pytest.mark.parametrize("proposal", [0, 1])
 def test_sampler_distribution_4x4(ham4, theta4, enum4, proposal):
-    """Brute force: the chains' histogram of |staggered magnetisation| and
-    their mean local energy match |psi|^2 over all 12870 states."""
+    """Brute force: independent chains sample |psi|^2 over all 12870 states
+    (the histogram over every state, equal-mass bins and a random partition
+    of the states), the histogram of |staggered magnetisation|, and the mean
+    local energy against the exact <H>.  The same samples must fail against
+    |psi|^1 (the acceptance ratio W'/W instead of (W'/W)^2 of Sec. 3.1), so
+    the checks can tell the two apart."""
     H, states = ham4
     la, sg, el = enum4
-    chains = 2048
-    s, lab, nacc, _ = R.sample(M4, theta4, neel(4, chains), n_sweeps=60, seed=1234,
+    chains = 8192
+    s, lab, nacc, _ = R.sample(M4, theta4, neel(4, chains), n_sweeps=80, seed=1234,
                                proposal=proposal)
     assert (s.sum(axis=1) == 0).all()
     np.testing.assert_allclose(lab, R.log_psi(M4, theta4, s)[0], rtol=1e-12)
     assert (nacc > 0).all()
     p = np.exp(2 * (la - la.max()))
     p /= p.sum()
+    stats = check_histogram(s, states, p)
+    print(stats)
+    p1 = np.exp(la - la.max())
+    with pytest.raises(AssertionError):
+        check_histogram(s, states, p1 / p1.sum())
     ms = _stag(states, 4)
     hist = np.bincount(_stag(s, 4), minlength=9)[:9]
     exp = np.array([p[ms == k].sum() for k in range(9)]) * chains
