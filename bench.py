@@ -66,7 +66,10 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
 
 
 WORKLOADS = {
-    "10x10": dict(L=10, C=16, n=6, B=4096, spins="sampled", sr="chol32"),
+    # S accumulated on the FP32 matrix cores is not positive definite at
+    # eps = 1e-4 on the sampled O (the factorisation reports it), so the
+    # explicit S is formed on the FP64 matrix cores; chol32 stays a variant
+    "10x10": dict(L=10, C=16, n=6, B=4096, spins="sampled", sr="chol64"),
     "16x16": dict(L=16, C=32, n=8, B=8192, spins="uniform", sr="cg"),
     "24x24": dict(L=24, C=32, n=8, B=16384, spins="uniform", sr="cg"),
 }
@@ -85,6 +88,16 @@ def sr_opts(V, name):
     }[name]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(wl, th, spins, sample):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle as R
@@ -97,8 +110,37 @@ def cpu_baseline(wl, th, spins, sample):
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": sample / dt, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "first %d of the %d configurations: E_loc + O_k + exact SR solve on that "
                       "subset, FP64 plain loops (%.1f s)" % (sample, len(spins), dt)}
+
+
+def cpu_extra():
+    """Oracle timings of the SR algebra at full size (host-memory bound; a
+    few minutes of CPU): the exact 10x10 solve by both exact forms on a
+    seeded O (B = 4096, P = 14080), and one application of S + eps I at
+    24x24 (B = 16384, P = 74304), the work of one CG iteration."""
+    import oracle as R
+    out = {"cpu_model": cpu_model(), "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+    rng = np.random.default_rng(3)
+    B, P = 4096, 14080
+    O = rng.standard_normal((B, P)) * 0.1
+    E = rng.standard_normal(B) - 50
+    for name, method in (("sample_space", 1), ("explicit_S", 0)):
+        t0 = time.perf_counter()
+        R.sr_solve(O, E, 1e-4, method=method)
+        out["sr_10x10_" + name + "_s"] = time.perf_counter() - t0
+        print(json.dumps({"cpu_extra": name, "s": out["sr_10x10_" + name + "_s"]}), flush=True)
+    del O
+    B, P = 16384, 74304
+    O = np.full((B, P), 0.5)
+    mean = O.mean(axis=0)
+    v = np.ones(P)
+    t0 = time.perf_counter()
+    R.sr_apply(O, mean, v, 1e-4)
+    out["sr_apply_24x24_s"] = time.perf_counter() - t0
+    out["sr_apply_24x24_gbs"] = 2 * B * P * 8 / out["sr_apply_24x24_s"] / 1e9
+    return out
 
 
 TRAFFIC_RECORDS = os.path.join(ROOT, "profiles", "hbm_traffic.md")
@@ -150,10 +192,10 @@ def copy_calibration(mib):
 
 def other_workload(V, torch, name, convs):
     """One full step of another workload (uniform Sz = 0 configurations) per
-    convolution form: samples/s and stage times, for the second lattice the
-    metric names.  One warm-up step, one timed step per form; then the other
-    SR form (the exact sample-space solve beside CG, or CG beside an exact
-    solve) on the same system, timed on its own."""
+    convolution form: samples/s and stage times, for the other lattices the
+    metric names.  One warm-up step, one timed step per form; then the exact
+    sample-space solve of each form's system, timed once, beside CG, and the
+    distance of the CG solution from it."""
     from vqmc_inputs import init_theta, uniform_sz0
     wl = WORKLOADS[name]
     L, C, n, B = wl["L"], wl["C"], wl["n"], wl["B"]
@@ -170,7 +212,10 @@ def other_workload(V, torch, name, convs):
     ws_o = torch.empty(max(V.log_derivs_workspace(base, B), 1), dtype=torch.uint8, device=dev)
     opts = sr_opts(V, wl["sr"])
     ws_sr = torch.empty(max(V.sr_workspace(B, P, opts), 1), dtype=torch.uint8, device=dev)
+    exact = sr_opts(V, "dual")
+    ws_x = torch.empty(max(V.sr_workspace(B, P, exact), 1), dtype=torch.uint8, device=dev)
     delta = torch.empty(P, dtype=torch.float64, device=dev)
+    dx = torch.empty(P, dtype=torch.float64, device=dev)
     for conv in convs:
         gm = base.with_prec(conv)
         lightcone = V.local_energy_method(gm) == V.ELOC_LIGHTCONE
@@ -191,37 +236,40 @@ def other_workload(V, torch, name, convs):
             wall = time.perf_counter() - t0
         st = [ev[j].elapsed_time(ev[j + 1]) for j in range(3)]
         fa, fe = eloc_flops(spins_np, L, C, n, lightcone, conv)
-        res[conv] = {"samples_per_s": B / wall, "ms_per_step": wall * 1e3,
-                     "stage_ms": {"local_energy": st[0], "log_derivs": st[1], "sr_solve": st[2]},
-                     "eloc": "lightcone" if lightcone else "dense",
-                     "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
-                     "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12}
+        r = {"samples_per_s": B / wall, "ms_per_step": wall * 1e3,
+             "stage_ms": {"local_energy": st[0], "log_derivs": st[1], "sr_solve": st[2]},
+             "eloc": "lightcone" if lightcone else "dense",
+             "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
+             "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12}
         if wl["sr"] == "cg":
-            res[conv].update({"cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
-                              "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9})
+            r.update({"cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
+                      "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9})
+        # the exact solution of the same system (sample-space Cholesky, FP64)
+        evx = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        evx[0].record()
+        V.vqmc_sr_solve(O, e, exact, delta=dx, workspace=ws_x, want_info=False)
+        evx[1].record()
+        torch.cuda.synchronize()
+        r["delta_rel_err_vs_exact"] = (torch.linalg.vector_norm(delta - dx) / torch.linalg.vector_norm(dx)).item()
+        if "sr_exact" not in res:
+            ms = evx[0].elapsed_time(evx[1])
+            # lower half of the B x B Gram matrix: B^2 P FLOPs on the FP64 matrix cores
+            res["sr_exact"] = {"form": SR_NAMES["dual"], "sr_solve_ms_first_call": ms,
+                               "gram_tflop": B * B * P / 1e12}
+        res[conv] = r
         del ws_e
-    # the other SR form on the last O, e
-    del ws_sr
-    other = "dual" if wl["sr"] == "cg" else "cg"
-    oo = sr_opts(V, other)
-    ws_c = torch.empty(max(V.sr_workspace(B, P, oo), 1), dtype=torch.uint8, device=dev)
-    for it in range(2):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        torch.cuda.synchronize()
-        ev[0].record()
-        _, _, oinfo = V.vqmc_sr_solve(O, e, oo, delta=delta, workspace=ws_c)
-        ev[1].record()
-        torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1])
-    if other == "dual":
-        # lower half of the B x B Gram matrix: B^2 P FLOPs on the FP64 matrix cores
-        res["sr_dual"] = {"sr_solve_ms": ms, "gram_tflop": B * B * P / 1e12,
-                          "gram_tflops": B * B * P / (ms / 1e3) / 1e12}
-    else:
-        res["sr_cg"] = {"sr_solve_ms": ms, "cg_iterations": oinfo["iters"],
-                        "cg_rel_residual": oinfo["rel_residual"],
-                        "cg_hbm_gbs": oinfo["iters"] * 2 * B * P * 4 / (ms / 1e3) / 1e9}
-    del ws_c
+    # the exact solve timed on its own, warm
+    evx = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    evx[0].record()
+    V.vqmc_sr_solve(O, e, exact, delta=dx, workspace=ws_x, want_info=False)
+    evx[1].record()
+    torch.cuda.synchronize()
+    ms = evx[0].elapsed_time(evx[1])
+    res["sr_exact"].update({"sr_solve_ms": ms, "gram_tflops": B * B * P / (ms / 1e3) / 1e12,
+                            "samples_per_s_with_exact_sr": {
+                                c: B / ((res[c]["stage_ms"]["local_energy"] + res[c]["stage_ms"]["log_derivs"]
+                                         + ms) / 1e3) for c in convs}})
+    del ws_sr, ws_x
     return res
 
 
@@ -238,16 +286,21 @@ def main():
     ap.add_argument("--burn-in", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="bf16x3,bf16,chol64,dual,sym",
+    ap.add_argument("--variants", default="bf16x3,bf16,chol32,dual,sym",
                     help="extra forms timed on the same inputs (comma list, or 'none')")
-    ap.add_argument("--also", default="24x24",
-                    help="another workload timed after the main one (one step per form, bf16x3, bf16 and fp32), "
-                         "or 'none'")
+    ap.add_argument("--also", default="24x24,16x16",
+                    help="other workloads timed after the main one (one step per form, bf16x3, bf16 and fp32; "
+                         "comma list), or 'none'")
+    ap.add_argument("--cpu-extra", action="store_true",
+                    help="only time the oracle's full-size SR algebra on the host (minutes), then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run the copy kernel that scales HBM byte counters, then exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.cpu_extra:
+        print(json.dumps({"cpu_extra": cpu_extra()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: libvqmc has no multi-GPU path "
@@ -334,6 +387,30 @@ def main():
 
     ms, stage = timed(gm, opts, ws_sr, args.steps, args.warmup)
     value = B / (ms / 1e3)
+    # after the timed region: the solve's report on the same inputs, and the
+    # distance of its delta from the exact FP64 sample-space solution of the
+    # same system (the reference every SR form is measured against here)
+    d_main = delta.clone()
+
+    def sr_status(o, ws):
+        """The solve's own report (status, CG iterations and residual) on the
+        current O and E, run once with info after the timed steps."""
+        try:
+            _, _, info = V.vqmc_sr_solve(O, e, o, delta=delta, F=F, workspace=ws)
+            info["status"] = "ok" if info["converged"] else V.STATUS[V.WARN_NOT_CONVERGED]
+        except V.VqmcError as err:
+            info = {"status": V.STATUS.get(err.status, str(err.status)), "iters": 0,
+                    "rel_residual": float("nan")}
+        return info
+    sr_info = sr_status(opts, ws_sr)
+    exact = sr_opts(V, "dual")
+    ws_x = torch.empty(max(V.sr_workspace(B, P, exact), 1), dtype=torch.uint8, device=dev)
+    d_exact = torch.empty(P, dtype=torch.float64, device=dev)
+    V.vqmc_sr_solve(O, e, exact, delta=d_exact, workspace=ws_x, want_info=False)
+    del ws_x
+
+    def delta_err(d):
+        return (torch.linalg.vector_norm(d - d_exact) / torch.linalg.vector_norm(d_exact)).item()
 
     # ---- roofline of the dominant kernel (the fused local-energy kernel:
     # one launch per call, so the call's event time is the kernel's time)
@@ -362,6 +439,11 @@ def main():
                       "L": L, "channels": C, "layers": n, "params": P, "samples": B,
                       "conv": args.conv, "sr": sr_name, "eloc": "lightcone" if lightcone else "dense"},
            "stage_ms": {"local_energy": stage[0], "log_derivs": stage[1], "sr_solve": stage[2]},
+           "sr_report": {"status": sr_info["status"],
+                         "iters": sr_info["iters"], "rel_residual": sr_info["rel_residual"],
+                         "delta_rel_err": delta_err(d_main),
+                         "delta_reference": "sample-space Cholesky, FP64, same O and E",
+                         "delta_bar": 1e-3, "meets_delta_bar": delta_err(d_main) <= 1e-3},
            "roofline": roof}
     if sampler:
         out["sampler"] = sampler
@@ -373,7 +455,8 @@ def main():
                 vms, vst = timed(gm.with_prec(v), opts, ws_sr, 1, 1)
                 variants["conv_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
                                          "stage_ms": vst.tolist(),
-                                         "eloc_tflops_algorithmic": flops_eloc / (vst[0] / 1e3) / 1e12}
+                                         "eloc_tflops_algorithmic": flops_eloc / (vst[0] / 1e3) / 1e12,
+                                         "delta_rel_err": delta_err(delta)}
             elif v in ("dense", "lightcone"):
                 vm = gm.with_eloc(V.ELOC_DENSE if v == "dense" else V.ELOC_LIGHTCONE)
                 if (v == "lightcone") == lightcone:
@@ -395,14 +478,19 @@ def main():
                 vws = torch.empty(max(V.sr_workspace(B, P, vo), 1), dtype=torch.uint8, device=dev)
                 vms, vst = timed(gm, vo, vws, 1, 1)
                 variants["sr_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
-                                       "stage_ms": vst.tolist()}
+                                       "stage_ms": vst.tolist(), "delta_rel_err": delta_err(delta),
+                                       "sr_status": sr_status(vo, vws)["status"]}
                 del vws
     if variants:
         out["variants"] = variants
-    if args.also != "none" and args.also != args.workload:
+    also = [w for w in args.also.split(",") if w not in ("none", "", args.workload)]
+    if also:
         del O, ws_o, ws_sr, ws_e
         torch.cuda.empty_cache()
-        out["also"] = other_workload(V, torch, args.also, ["bf16x3", "bf16", "fp32"])
+        out["also"] = {}
+        for w in also:
+            out["also"][w] = other_workload(V, torch, w, ["bf16x3", "bf16", "fp32"])
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, th_np, spins_np, min(args.cpu_sample, B))
     print(json.dumps(out), flush=True)
