@@ -158,6 +158,22 @@ vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta,
                               int32_t *chain_flags, void *workspace,
                               size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the local energy
+ * of vqmc_local_energy in the dense evaluation, with the packed layer weights
+ * kept in the library's own device array (576 KiB per GPU, taken on the first
+ * call on a device and held until the process ends) instead of a workspace.
+ * Same arguments and results as vqmc_local_energy with eloc_mode DENSE (AUTO
+ * is taken as DENSE); VQMC_ERR_ARG for symmetry = 1 or eloc_mode LIGHTCONE,
+ * which need a caller workspace; VQMC_ERR_WORKSPACE if the model's packed
+ * weights exceed the array (never for the models vqmc_num_params accepts);
+ * VQMC_ERR_DEVICE if the array's address cannot be obtained.  The call
+ * allocates nothing.  Every call on a GPU uses that GPU's one array: calls
+ * that overlap on one GPU (several streams or host threads) race. */
+vqmc_status vqmc_local_energy_noalloc(const vqmc_model *m, const float *theta,
+                                      const int8_t *spins, int32_t B, double *e_loc,
+                                      int32_t *chain_flags, hipStream_t stream);
+
 /* The method vqmc_local_energy uses for this model (*method: VQMC_ELOC_DENSE
  * or VQMC_ELOC_LIGHTCONE, AUTO resolved); VQMC_ERR_ARG when the model asks
  * for the light cone and the light cone does not support it. */

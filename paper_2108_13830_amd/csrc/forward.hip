@@ -1,6 +1,8 @@
 // forward.hip -- log|psi|, the local-energy generator and the Metropolis
 // exchange sampler, all built on the fused conv engine (engine.hpp).
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 #include <stdint.h>
 
@@ -712,6 +714,58 @@ extern "C" vqmc_status vqmc_local_energy(const vqmc_model *m, const float *theta
   sym_combine_kernel<<<(B + 255) / 256, 256, 0, stream>>>(e4, lp4, f4, B, e_loc, chain_flags);
   VQMC_LAUNCH_CHECK();
   return VQMC_OK;
+}
+
+// ------------------------------------------------- allocation-free variant
+
+namespace vqmc {
+
+// Room for the C -> C layers' packed fragments of the dense local energy for
+// every supported model: kMaxLayers layers of the largest engine (C = 32,
+// split-BF16: 36 KiB per layer, 576 KiB in all).
+constexpr size_t kScratchBytes = (size_t)kMaxLayers * Engine<32, P_X3, 1, 1>::FRAG_LAYER;
+static_assert(kScratchBytes <= (1u << 20), "the no-allocation scratch stays below 1 MiB");
+
+// The library's own device memory for vqmc_local_energy_noalloc, one copy
+// per GPU, held until the process ends.  Its host-side name is not a device
+// address: host code uses the per-device pointer from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void *g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (with the device current) and kept; nullptr on failure.
+static void *scratch_ptr() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace vqmc
+
+extern "C" vqmc_status vqmc_local_energy_noalloc(const vqmc_model *m, const float *theta, const int8_t *spins,
+                                                 int32_t B, double *e_loc, int32_t *chain_flags,
+                                                 hipStream_t stream) {
+  if (!model_valid(m)) return VQMC_ERR_ARG;
+  if (m->symmetry || m->eloc_mode == VQMC_ELOC_LIGHTCONE) return VQMC_ERR_ARG;
+  if (B < 0) return VQMC_ERR_SHAPE;
+  if (B > 0 && (!theta || !spins || !e_loc)) return VQMC_ERR_ARG;
+  vqmc_model dm = *m;
+  dm.eloc_mode = VQMC_ELOC_DENSE;
+  const size_t need = dense_ws_bytes(&dm);
+  if (need > kScratchBytes) return VQMC_ERR_WORKSPACE;
+  if (B == 0) return VQMC_OK;
+  void *ws = need ? scratch_ptr() : nullptr;
+  if (need && !ws) return VQMC_ERR_DEVICE;
+  return eloc_plain(&dm, theta, spins, B, e_loc, chain_flags, nullptr, ws, need, stream);
 }
 
 extern "C" vqmc_status vqmc_sample(const vqmc_model *m, const float *theta, int8_t *spins,

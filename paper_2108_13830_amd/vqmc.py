@@ -111,6 +111,7 @@ SIGNATURES = [
     ("vqmc_log_psi", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP]),
     ("vqmc_local_energy", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP,
                                      ct.c_size_t, _VP]),
+    ("vqmc_local_energy_noalloc", ct.c_int, [ct.POINTER(_Model), _VP, _VP, ct.c_int32, _VP, _VP, _VP]),
     ("vqmc_local_energy_method", ct.c_int, [ct.POINTER(_Model), ct.POINTER(ct.c_int32)]),
     ("vqmc_local_energy_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32,
                                                ct.POINTER(ct.c_size_t)]),
@@ -231,6 +232,23 @@ def vqmc_local_energy(m: Model, theta, spins, out=None, flags=None, workspace=No
     _check("vqmc_local_energy", lib().vqmc_local_energy(
         ct.byref(mc), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(flags), _ptr(workspace),
         0 if workspace is None else workspace.numel(), _stream()))
+    return out
+
+
+def vqmc_local_energy_noalloc(m: Model, theta, spins, out=None, flags=None):
+    """The local energy in the dense evaluation with no workspace: the
+    library keeps the packed weights in its own device array (for callers
+    that cannot allocate device memory)."""
+    B = spins.shape[0]
+    _dev(theta, torch.float32, "theta", (num_params(m),))
+    _dev(spins, torch.int8, "spins", (B, m.N))
+    if out is None:
+        out = torch.empty(B, dtype=torch.float64, device=spins.device)
+    _dev(out, torch.float64, "out", (B,))
+    _dev(flags, torch.int32, "flags", (B,))
+    mc = m.c()
+    _check("vqmc_local_energy_noalloc", lib().vqmc_local_energy_noalloc(
+        ct.byref(mc), _ptr(theta), _ptr(spins), B, _ptr(out), _ptr(flags), _stream()))
     return out
 
 

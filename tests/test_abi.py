@@ -23,7 +23,7 @@ def declared():
 
 def test_every_declared_symbol_is_exported():
     names = declared()
-    assert len(names) == 13
+    assert len(names) == 14
     lib = ct.CDLL(V.LIB_PATH)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
@@ -56,6 +56,14 @@ def test_argument_errors_need_no_gpu():
     nul = ct.c_void_p(0)
     assert lib.vqmc_log_psi(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
     assert lib.vqmc_local_energy(ct.byref(bad), nul, nul, 1, nul, nul, nul, 0, nul) == 1
+    assert lib.vqmc_local_energy_noalloc(ct.byref(bad), nul, nul, 1, nul, nul, nul) == 1
+    # the allocation-free form: dense only, no symmetrisation, checked arguments
+    sym = V.Model(4, 4, 2, symmetry=1).c()
+    lc = V.Model(16, 16, 2, eloc=V.ELOC_LIGHTCONE).c()
+    assert lib.vqmc_local_energy_noalloc(ct.byref(sym), nul, nul, 1, nul, nul, nul) == 1
+    assert lib.vqmc_local_energy_noalloc(ct.byref(lc), nul, nul, 1, nul, nul, nul) == 1
+    assert lib.vqmc_local_energy_noalloc(ct.byref(good), nul, nul, -1, nul, nul, nul) == 2
+    assert lib.vqmc_local_energy_noalloc(ct.byref(good), nul, nul, 3, nul, nul, nul) == 1
     assert lib.vqmc_log_psi(ct.byref(good), nul, nul, -1, nul, nul, nul) == 2
     assert lib.vqmc_log_psi(ct.byref(good), nul, nul, 3, nul, nul, nul) == 1
     # B = 0 is a valid empty call: nothing is launched
