@@ -284,7 +284,7 @@ def main():
     ap.add_argument("--eloc", default="auto", choices=["auto", "dense", "lightcone"])
     ap.add_argument("--samples", type=int, default=None, help="override B")
     ap.add_argument("--burn-in", type=int, default=1000)
-    ap.add_argument("--cpu-sample", type=int, default=160)
+    ap.add_argument("--cpu-sample", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="bf16x3,bf16,chol32,dual,sym",
                     help="extra forms timed on the same inputs (comma list, or 'none')")

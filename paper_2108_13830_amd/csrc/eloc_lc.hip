@@ -211,18 +211,10 @@ __device__ __forceinline__ void dstore4(char *buf, int cap, int row, int co0, co
   } else {
     uint16_t *hi = reinterpret_cast<uint16_t *>(buf);
     const int pi = E::phys(row, co0);
-    uint16_t b[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = bf16_rne(h[j]);
-    *reinterpret_cast<uint2 *>(hi + pi) =
-        uint2{(uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16)};
-    if constexpr (PREC == P_X3) {
-      uint16_t c[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) c[j] = bf16_rne(h[j] - bf16_f32(b[j]));
-      *reinterpret_cast<uint2 *>(hi + (cap + 1) * C + pi) =
-          uint2{(uint32_t)c[0] | ((uint32_t)c[1] << 16), (uint32_t)c[2] | ((uint32_t)c[3] << 16)};
-    }
+    uint2 vh, vl;
+    bf16_split4<PREC == P_X3>(h, vh, vl);
+    *reinterpret_cast<uint2 *>(hi + pi) = vh;
+    if constexpr (PREC == P_X3) *reinterpret_cast<uint2 *>(hi + (cap + 1) * C + pi) = vl;
   }
 }
 

@@ -57,6 +57,27 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats rounded to nearest-even BF16 by one packed conversion: a in the
+// low half, b in the high half.
+__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t{a, b}), bf16x2_t));
+}
+
+// Four consecutive values as BF16 pairs hi = bf16(h) and, for the split form,
+// lo = bf16(h - hi) (the subtractions are plain FP32 ones).
+template <bool SPLIT>
+__device__ __forceinline__ void bf16_split4(const float (&h)[4], uint2 &hi, uint2 &lo) {
+  hi = uint2{bf16x2_rne(h[0], h[1]), bf16x2_rne(h[2], h[3])};
+  if constexpr (SPLIT) {
+    const float r0 = h[0] - __uint_as_float(hi.x << 16), r1 = h[1] - __uint_as_float(hi.x & 0xffff0000u);
+    const float r2 = h[2] - __uint_as_float(hi.y << 16), r3 = h[3] - __uint_as_float(hi.y & 0xffff0000u);
+    lo = uint2{bf16x2_rne(r0, r1), bf16x2_rne(r2, r3)};
+  }
+}
+
 __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -164,18 +185,10 @@ struct Engine {
     } else {
       uint16_t *hi = reinterpret_cast<uint16_t *>(act);
       const int pi = phys(row, co0);
-      uint16_t b[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = bf16_rne(h[j]);
-      *reinterpret_cast<uint2 *>(hi + pi) =
-          uint2{(uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16)};
-      if constexpr (X3) {
-        uint16_t c[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[j] = bf16_rne(h[j] - bf16_f32(b[j]));
-        *reinterpret_cast<uint2 *>(hi + MAXROWS * C + pi) =
-            uint2{(uint32_t)c[0] | ((uint32_t)c[1] << 16), (uint32_t)c[2] | ((uint32_t)c[3] << 16)};
-      }
+      uint2 vh, vl;
+      bf16_split4<X3>(h, vh, vl);
+      *reinterpret_cast<uint2 *>(hi + pi) = vh;
+      if constexpr (X3) *reinterpret_cast<uint2 *>(hi + MAXROWS * C + pi) = vl;
     }
   }
 
