@@ -41,16 +41,39 @@ def antiparallel_counts(spins, L):
 
 
 def eloc_flops(spins, L, C, n, lightcone, conv):
-    """(algorithmic, executed-on-matrix-cores) FLOPs of one local-energy call.
-    Dense: (1 + n_ap) forward passes per sample.  Light cone: one forward
-    pass per sample plus, per exchanged pair and layer, the convolution rows
-    of the pair's neighbourhood at that distance (executed: rows padded to
-    16-row tiles; split-BF16 executes three products)."""
+    """(algorithmic, executed) FLOPs of one local-energy call.
+
+    Algorithmic: dense, (1 + n_ap) forward passes per sample; light cone, one
+    forward pass per sample plus, per exchanged pair and layer, the
+    convolution rows of the pair's neighbourhood at that distance.
+
+    Executed: the products the matrix cores run in the convolution precision,
+    counted as the kernels issue them.  Dense: every batch of G = rows / N
+    configurations runs all rows of the workgroup (448 in the C = 16 BF16
+    forms at up to 448 sites, else 512 at C <= 16 and 576 at C = 32), with K
+    padded to whole instruction steps (4 for FP32, 32 for BF16: 144 -> 160 at
+    C = 16), plus, for FP32, the 1 -> C lift (K = 9 padded to 12; in the BF16
+    forms the lift runs on the FP32 matrix cores and is not counted here).
+    Light cone: the neighbourhood rows padded to 16-row tiles (the FP32 pass
+    of the sampled configuration is counted only for the FP32 form).
+    Split-BF16 runs three products per output."""
     nap = antiparallel_counts(spins, L)
     mult = 3 if conv == "bf16x3" else 1
+    N = L * L
+    B = spins.shape[0]
     if not lightcone:
         f = float((1 + nap.sum(axis=1)).sum()) * f_cfg(L, C, n)
-        return f, f * mult
+        if conv == "fp32":
+            kstep, rows = 4, 4 * (9 if C == 32 else 8) * 16
+        else:
+            kstep = 32
+            rows = 4 * 7 * 16 if (C == 16 and N <= 448) else 4 * (9 if C == 32 else 8) * 16
+        G = min(rows // N, 64)
+        kpad = -(-9 * C // kstep) * kstep
+        ntc = -(-C // 16) * 16
+        per_batch = rows * ntc * 2 * n * kpad + (rows * ntc * 2 * 12 if conv == "fp32" else 0)
+        batches = float((-(-(1 + nap.sum(axis=1)) // G)).sum())
+        return f, batches * per_batch * mult
     per_row = 2 * 9 * C * C
     alg = np.zeros(4)
     exe = np.zeros(4)
@@ -60,9 +83,8 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
             rows = min(ey + 1 + 2 * d, L) * min(ex + 1 + 2 * d, L)
             alg[kind] += rows * per_row
             exe[kind] += -(-rows // 16) * 16 * per_row
-    B = spins.shape[0]
     base = B * f_cfg(L, C, n)
-    return base + float((nap * alg).sum()), base + float((nap * exe).sum()) * mult
+    return base + float((nap * alg).sum()), (base if conv == "fp32" else 0.0) + float((nap * exe).sum()) * mult
 
 
 WORKLOADS = {
@@ -240,7 +262,8 @@ def other_workload(V, torch, name, convs):
              "stage_ms": {"local_energy": st[0], "log_derivs": st[1], "sr_solve": st[2]},
              "eloc": "lightcone" if lightcone else "dense",
              "eloc_tflops_algorithmic": fa / (st[0] / 1e3) / 1e12,
-             "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12}
+             "eloc_tflops_executed": fe / (st[0] / 1e3) / 1e12,
+             "eloc_executed_frac_of_peak": fe / (st[0] / 1e3) / 1e12 / PEAK[conv]}
         if wl["sr"] == "cg":
             r.update({"cg_iterations": info["iters"], "cg_rel_residual": info["rel_residual"],
                       "cg_hbm_gbs": info["iters"] * 2 * B * P * 4 / (st[2] / 1e3) / 1e9})
@@ -453,9 +476,13 @@ def main():
         for v in args.variants.split(","):
             if v in ("bf16", "bf16x3", "fp32") and v != args.conv:
                 vms, vst = timed(gm.with_prec(v), opts, ws_sr, 1, 1)
+                lc_v = V.local_energy_method(gm.with_prec(v)) == V.ELOC_LIGHTCONE
+                _, fe_v = eloc_flops(spins_np, L, C, n, lc_v, v)
                 variants["conv_" + v] = {"samples_per_s": B / (vms / 1e3), "ms_per_step": vms,
                                          "stage_ms": vst.tolist(),
                                          "eloc_tflops_algorithmic": flops_eloc / (vst[0] / 1e3) / 1e12,
+                                         "eloc_tflops_executed": fe_v / (vst[0] / 1e3) / 1e12,
+                                         "eloc_executed_frac_of_peak": fe_v / (vst[0] / 1e3) / 1e12 / PEAK[v],
                                          "delta_rel_err": delta_err(delta)}
             elif v in ("dense", "lightcone"):
                 vm = gm.with_eloc(V.ELOC_DENSE if v == "dense" else V.ELOC_LIGHTCONE)

@@ -17,7 +17,8 @@
  * process ends) on which that solve overlaps part of its trailing updates
  * with the factorisation of the next panel; the call's own stream waits for
  * that work before the call's remaining kernels, so the call still behaves
- * as work enqueued on its own stream.
+ * as work enqueued on its own stream.  On a stream under HIP graph capture
+ * the solve uses no side stream (every kernel goes to the captured stream).
  *
  * Layouts (a specification the FP64 test oracle also follows):
  *   - site i = y*L + x, periodic boundaries, spin +1 = up, -1 = down (Sec. 2.1);

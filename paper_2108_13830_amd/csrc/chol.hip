@@ -756,7 +756,10 @@ vqmc_status chol_factor_solve(double *M, int64_t n, int64_t ld, double *x, void 
   if (n < 1 || ld < n || (ld & 1) || (reinterpret_cast<uintptr_t>(M) & 15)) return VQMC_ERR_ARG;
   double *Linv = reinterpret_cast<double *>(ws);
   const int64_t nr = n + 1;  // rows of the augmented matrix; row n carries the right-hand side
-  Side *sd = n > 2 * OB ? side_for_current_device() : nullptr;
+  // a stream under graph capture gets every kernel itself (no side stream)
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return VQMC_ERR_DEVICE;
+  Side *sd = (n > 2 * OB && cap == hipStreamCaptureStatusNone) ? side_for_current_device() : nullptr;
   std::unique_lock<std::mutex> hold;
   if (sd) hold = std::unique_lock<std::mutex>(sd->mu);
   bool rest_pending = false;
