@@ -189,6 +189,7 @@ __device__ __forceinline__ void diag_factor(double *__restrict__ M, int64_t n, i
 __global__ __launch_bounds__(256) void chol_diag_kernel(double *__restrict__ M, int64_t n, int64_t ld, int64_t c0,
                                                        double *__restrict__ Linv, int *__restrict__ status,
                                                        double *__restrict__ side) {
+  __builtin_amdgcn_s_setprio(3);
   __shared__ double colbuf[2][CB];
   if (side)
     for (int idx = threadIdx.x; idx < CB * CB; idx += 256) {
@@ -322,6 +323,9 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double *__restrict__ M, 
                                                         double *__restrict__ Linv1, int *__restrict__ status,
                                                         const double *__restrict__ side_in,
                                                         double *__restrict__ side_out) {
+  // the panel chain's waves issue ahead of the concurrent trailing update's
+  // on a shared compute unit
+  __builtin_amdgcn_s_setprio(3);
   __shared__ double sX[CB][CB + 2];
   __shared__ double sY[CB][CB + 2];
   __shared__ double colbuf[2][CB];
@@ -556,6 +560,7 @@ __global__ __launch_bounds__(256, 2) void chol_next_panel_kernel(double *__restr
                                                                double *__restrict__ side) {
   __shared__ double sX[CB][CB + 2];
   __shared__ double sY[CB][CB + 2];
+  __builtin_amdgcn_s_setprio(3);  // on the chain between two outer panels
   const int bi = (int)blockIdx.x / ncb, bj = (int)blockIdx.x - bi * ncb;
   const int64_t r0 = p1 + (int64_t)bi * CB, c0 = p1 + (int64_t)bj * CB;
   if (bj > bi || c0 >= n) return;  // uniform per workgroup
