@@ -22,6 +22,13 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
+# extra flags per source: the matrix-core probe keeps its accumulators in
+# ordinary VGPRs, so that its loop is the instructions alone (with the
+# accumulation registers the compiler copies every accumulator once per
+# iteration there)
+EXTRA = {"probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith(".hip") or f.endswith(".cpp"))
@@ -30,7 +37,7 @@ def sources():
 def _compile(src: str, objdir: str, verbose: bool) -> str:
     obj = os.path.join(objdir, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + CFLAGS + lang + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + EXTRA.get(os.path.basename(src), []) + lang + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

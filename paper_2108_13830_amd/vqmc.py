@@ -129,6 +129,8 @@ SIGNATURES = [
                                  ct.c_size_t, ct.POINTER(_SrInfo), _VP]),
     ("vqmc_vmc_step_workspace", ct.c_int, [ct.POINTER(_Model), ct.c_int32, ct.POINTER(_SrOpts),
                                            ct.POINTER(ct.c_size_t)]),
+    # measurement helper (include/vqmc_probe.h)
+    ("vqmc_probe_mfma", ct.c_int, [ct.c_int, ct.c_int, ct.c_int, _VP, _VP, ct.POINTER(ct.c_double), _VP]),
 ]
 
 
@@ -363,6 +365,28 @@ def vqmc_vmc_step(m: Model, theta, spins, n_sweeps: int, seed: int, counter_base
         return None
     return dict(e_mean=info.e_mean, e_var=info.e_var, iters=info.iters, rel_residual=info.rel_residual,
                 converged=(rc == 0))
+
+
+PROBE_KINDS = {"bf16": 0, "bf16x3": 0, "fp32": 1, "fp64": 2}
+
+
+def probe_mfma(kind: str, iters: int = 20000, blocks: int = 2048) -> float:
+    """Achievable matrix-core TFLOP/s of one instruction kind on the current
+    GPU (vqmc_probe_mfma timed with HIP events on the current stream; one
+    warm-up launch)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    x = torch.linspace(0.5, 1.5, 128, dtype=torch.float32, device=dev)
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    fl = ct.c_double(0.0)
+    k = PROBE_KINDS[kind]
+    _check("vqmc_probe_mfma", lib().vqmc_probe_mfma(k, 10, blocks, _ptr(x), _ptr(out), None, _stream()))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _check("vqmc_probe_mfma", lib().vqmc_probe_mfma(k, iters, blocks, _ptr(x), _ptr(out), ct.byref(fl),
+                                                     _stream()))
+    e1.record()
+    torch.cuda.synchronize()
+    return fl.value / (e0.elapsed_time(e1) / 1e3) / 1e12
 
 
 class LogPsi(torch.autograd.Function):
