@@ -23,6 +23,9 @@
 
 namespace vqmc {
 
+// samples per K chunk of the direct-to-LDS S product
+constexpr int SYRK_KC = 16;
+
 // v_mfma_f64_16x16x4f64: A[m = lane%16][k = lane/16], B[k = lane/16][n = lane%16],
 // D register i of lane l holds D[row = l/16 + 4 i][col = l%16].
 __device__ __forceinline__ f64x4 mma_f64(double a, double b, f64x4 c) {
@@ -279,6 +282,104 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ 
   typename TT::acc_t acc[4][4];
   TT::zero(acc);
   run_sided<T, KC, true>(ldr, (B + KC - 1) / KC, sA, sB, acc);
+  const double inv = 1.0 / B;
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + TT::row_of(tm, r), col = j0 + TT::col_of(tn);
+        if (row < P && col <= row) S[row * ldS + col] = (double)acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
+      }
+}
+
+// The explicit S on the same 128 x 128 tiles, with the operand panels copied
+// from O straight into LDS (direct-to-LDS loads: no registers, no stores) in
+// two buffers, so that the copy of chunk c + 1 runs while the matrix cores
+// consume chunk c and one barrier per chunk suffices.  A panel chunk is KC
+// samples (rows k) of 128 parameters; the 16-float blocks of row k sit at
+// block ^ (k & 3), so that the four rows one operand read spans fall on
+// disjoint LDS banks.  Operands are centred as they are read, in FP64, and
+// then rounded to T: the same values as syrk_kernel forms, hence the same S.
+// Needs 16-byte loads (P % 4 == 0, rows 16-byte aligned); rows past B in the
+// last chunk read row B - 1 and enter as zeros.
+template <typename T, int KC>
+__global__ __launch_bounds__(256, 2) void syrk_dma_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
+                                                       const double *__restrict__ obar, double eps,
+                                                       double *__restrict__ S, int64_t ldS, int ntiles) {
+  static_assert(KC % 8 == 0, "a chunk is whole row pairs for each wave");
+  constexpr int PANEL = KC * 128;  // floats per panel chunk
+  constexpr int PAIRS = KC / 2;    // wave copy instructions per panel chunk (two rows each)
+  __shared__ __align__(16) float sbuf[2][2][PANEL];
+  using TT = Tile128<T>;
+  int bi, bj;
+  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
+  const int64_t i0 = (int64_t)bi * 128, j0 = (int64_t)bj * 128;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave >> 1, wn = wave & 1, g = lane >> 4, li = lane & 15;
+  // copies: instruction q = wave + 4 j of a chunk moves rows 2 (q % PAIRS) and
+  // + 1 of panel q / PAIRS; row & 3 = 2 (wave & 1) + lane / 32 for all of
+  // this lane's, so its source column (logical 4-float unit lu of its
+  // physical unit lane % 32) is fixed
+  const int prow = lane >> 5, pu = lane & 31;
+  const int lu = (((pu >> 2) ^ (2 * (wave & 1) + prow)) << 2) | (pu & 3);
+  const int64_t colA = i0 + 4 * lu <= P - 4 ? i0 + 4 * lu : P - 4;
+  const int64_t colB = j0 + 4 * lu <= P - 4 ? j0 + 4 * lu : P - 4;
+  auto copy = [&](int c, int buf) {
+#pragma unroll
+    for (int j = 0; j < KC / 4; ++j) {
+      const int q = wave + 4 * j, side = q / PAIRS, pair = q - side * PAIRS;
+      const int b0 = c * KC + 2 * pair + prow;
+      const int b = b0 < B ? b0 : B - 1;
+      const float *src = O + (int64_t)b * ldO + (side ? colB : colA);
+      __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(&sbuf[buf][side][pair * 256]), 16, 0, 0);
+    }
+  };
+  // operand reads: row k = 4 ks + g (k & 3 = g), logical block wm * 4 + t
+  int offA[4], offB[4];
+  double oba[4], obb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    offA[t] = g * 128 + (((wm * 4 + t) ^ g) << 4) + li;
+    offB[t] = g * 128 + (((wn * 4 + t) ^ g) << 4) + li;
+    const int64_t ca = i0 + wm * 64 + t * 16 + li, cb = j0 + wn * 64 + t * 16 + li;
+    oba[t] = ca < P ? obar[ca] : 0.0;
+    obb[t] = cb < P ? obar[cb] : 0.0;
+  }
+  typename TT::acc_t acc[4][4];
+  TT::zero(acc);
+  auto chunk = [&](const float *pa, const float *pb, int kleft, auto tail) {
+    constexpr bool TAIL = decltype(tail)::value;
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      T a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double x = (double)pa[offA[t] + ks * 512] - oba[t];
+        a[t] = (T)(TAIL && 4 * ks + g >= kleft ? 0.0 : x);
+        b[t] = (T)((double)pb[offB[t] + ks * 512] - obb[t]);
+      }
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = TT::mma(a[tm], b[tn], acc[tm][tn]);
+    }
+  };
+  // whole chunks, then (B % KC != 0) the last, partial one
+  const int nfull = B / KC, nchunks = (B + KC - 1) / KC;
+  copy(0, 0);
+  for (int c = 0; c < nfull; ++c) {
+    wait_copies();
+    __syncthreads();
+    if (c + 1 < nchunks) copy(c + 1, (c + 1) & 1);
+    chunk(sbuf[c & 1][0], sbuf[c & 1][1], KC, std::false_type{});
+  }
+  if (nfull < nchunks) {
+    wait_copies();
+    __syncthreads();
+    chunk(sbuf[nfull & 1][0], sbuf[nfull & 1][1], B - nfull * KC, std::true_type{});
+  }
   const double inv = 1.0 / B;
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
@@ -679,10 +780,10 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     const int64_t T = (P + 127) / 128, ldS = ld_even(P);
     const int nt = (int)(T * (T + 1) / 2);
     if (o->s_prec == 1) {
-      if (tvec) syrk_kernel<double, true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      if (tvec) syrk_dma_kernel<double, SYRK_KC><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
       else syrk_kernel<double, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
     } else {
-      if (tvec) syrk_kernel<float, true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      if (tvec) syrk_dma_kernel<float, SYRK_KC><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
       else syrk_kernel<float, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
     }
     VQMC_LAUNCH_CHECK();
