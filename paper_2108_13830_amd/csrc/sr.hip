@@ -182,8 +182,9 @@ __global__ void col_sum_kernel(const double *__restrict__ part, int nch, int64_t
 // columns (fixed for the whole K loop) of KC/8 samples per chunk; samples past
 // B are zeroed at the LDS store, columns past P are clamped (they only feed
 // outputs that are not stored).  Centring happens in FP64 before the
-// rounding to T.
-template <typename T, int KC, bool VEC>
+// rounding to T.  Scalar loads: the form for O whose rows are not 16-byte
+// aligned or whose P is not a multiple of 4 (syrk_dma_kernel otherwise).
+template <typename T, int KC>
 struct SyrkLoader {
   static constexpr int NQ = KC / 8;
   const float *O;
@@ -215,13 +216,8 @@ struct SyrkLoader {
       const int k = (threadIdx.x >> 5) + 8 * q;
       const int b = c * KC + k;
       const float *row = O + (int64_t)(b < B ? b : B - 1) * ldO;
-      if constexpr (VEC) {
-        const float4 x = *reinterpret_cast<const float4 *>(row + (col <= P - 4 ? col : P - 4));
-        r.v[q][0] = x.x; r.v[q][1] = x.y; r.v[q][2] = x.z; r.v[q][3] = x.w;
-      } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) r.v[q][t] = row[col + t < P ? col + t : P - 1];
-      }
+      for (int t = 0; t < 4; ++t) r.v[q][t] = row[col + t < P ? col + t : P - 1];
     }
   }
   __device__ __forceinline__ void store(const Regs &r, Panel<T, KC, true> &Pn, bool bside) const {
@@ -268,7 +264,7 @@ __device__ __forceinline__ void run_sided(const LD &ld, int nchunks, Panel<T, KC
 // lower 128 x 128 blocks (row stride ldS).  T = double: FP64 operands and
 // accumulation; T = float: the centred values are rounded to FP32 and
 // accumulated by the FP32 matrix cores.
-template <typename T, bool VEC>
+template <typename T>
 __global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
                                                    const double *__restrict__ obar, double eps,
                                                    double *__restrict__ S, int64_t ldS, int ntiles) {
@@ -278,7 +274,7 @@ __global__ __launch_bounds__(256, 2) void syrk_kernel(const float *__restrict__ 
   int bi, bj;
   lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
   const int64_t i0 = (int64_t)bi * 128, j0 = (int64_t)bj * 128;
-  const SyrkLoader<T, KC, VEC> ldr(O, ldO, B, P, i0, j0, obar);
+  const SyrkLoader<T, KC> ldr(O, ldO, B, P, i0, j0, obar);
   typename TT::acc_t acc[4][4];
   TT::zero(acc);
   run_sided<T, KC, true>(ldr, (B + KC - 1) / KC, sA, sB, acc);
@@ -394,8 +390,8 @@ __global__ __launch_bounds__(256, 2) void syrk_dma_kernel(const float *__restric
 
 // Loader of the sample-space Gram tiles: panel rows are samples a0.. (A side)
 // or c0.. (B side), k runs over parameters in chunks of 16.  Samples past B
-// are clamped (outputs not stored); parameters past P are zeroed.
-template <bool VEC>
+// are clamped (outputs not stored); parameters past P are zeroed.  Scalar
+// loads: the form for O without 16-byte rows (gram_dma_kernel otherwise).
 struct GramLoader {
   const float *O;
   int64_t ldO;
@@ -419,13 +415,8 @@ struct GramLoader {
       const int m = (threadIdx.x + 256 * q) >> 2;
       const int a = (bside ? c0 : a0) + m;
       const float *row = O + (int64_t)(a < B ? a : B - 1) * ldO;
-      if constexpr (VEC) {
-        const float4 x = *reinterpret_cast<const float4 *>(row + (k <= P - 4 ? k : P - 4));
-        r.v[q][0] = x.x; r.v[q][1] = x.y; r.v[q][2] = x.z; r.v[q][3] = x.w;
-      } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) r.v[q][t] = row[k + t < P ? k + t : P - 1];
-      }
+      for (int t = 0; t < 4; ++t) r.v[q][t] = row[k + t < P ? k + t : P - 1];
     }
   }
   __device__ __forceinline__ void store(const Regs &r, Panel<double, 16, false> &Pn, bool) const {
@@ -445,7 +436,6 @@ struct GramLoader {
 
 // Sample-space Gram: K[a][c] = (1/B) sum_k (O[a][k]-<O_k>)(O[c][k]-<O_k>) + eps [a == c]
 // (row stride ldK).
-template <bool VEC>
 __global__ __launch_bounds__(256, 2) void gram_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
                                                    const double *__restrict__ obar, double eps,
                                                    double *__restrict__ K, int64_t ldK, int ntiles) {
@@ -454,10 +444,112 @@ __global__ __launch_bounds__(256, 2) void gram_kernel(const float *__restrict__ 
   int bi, bj;
   lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
   const int a0 = bi * 128, c0 = bj * 128;
-  const GramLoader<VEC> ldr{O, ldO, B, P, a0, c0, obar};
+  const GramLoader ldr{O, ldO, B, P, a0, c0, obar};
   TT::acc_t acc[4][4];
   TT::zero(acc);
   run_sided<double, 16, false>(ldr, (int)((P + 15) / 16), sA, sB, acc);
+  const double inv = 1.0 / B;
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = a0 + TT::row_of(tm, r), col = c0 + TT::col_of(tn);
+        if (row < B && col <= row) K[(int64_t)row * ldK + col] = acc[tm][tn][r] * inv + (row == col ? eps : 0.0);
+      }
+}
+
+// The sample-space Gram matrix with the same direct-to-LDS panel copies as
+// syrk_dma_kernel: panel rows are samples, a chunk is 16 parameters (k), so a
+// row of a chunk is four 16-byte units, unit u stored at u ^ ((m >> 2) & 3)
+// (an operand read then touches 64 distinct banks).  The means of the
+// chunk's parameters are loaded beside its copy; parameters past P in the
+// last chunk enter as zeros.  Needs 16-byte loads (P % 4 == 0, rows 16-byte
+// aligned); the same values enter the matrix cores as in gram_kernel.
+__global__ __launch_bounds__(256, 2) void gram_dma_kernel(const float *__restrict__ O, int64_t ldO, int B, int64_t P,
+                                                       const double *__restrict__ obar, double eps,
+                                                       double *__restrict__ K, int64_t ldK, int ntiles) {
+  constexpr int KC = 16, PANEL = 128 * KC;  // floats per panel chunk
+  __shared__ __align__(16) float sbuf[2][2][PANEL];
+  using TT = Tile128<double>;
+  int bi, bj;
+  lower_block(xcd_contiguous(blockIdx.x, ntiles), bi, bj);
+  const int a0 = bi * 128, c0 = bj * 128;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // copies: instruction q = wave + 4 j moves rows 16 (q % 8) .. + 15 of
+  // panel q / 8, the lane's row 16 (q % 8) + lane / 4, whose swizzle
+  // (row >> 2) & 3 = lane / 16: its source unit is fixed
+  const int su = (lane & 3) ^ (lane >> 4);
+  auto copy = [&](int c, int buf) {
+    const int64_t k0 = (int64_t)c * KC + 4 * su;
+    const int64_t kc = k0 <= P - 4 ? k0 : P - 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int q = wave + 4 * j, side = q >> 3, blk = q & 7;
+      const int row = (side ? c0 : a0) + 16 * blk + (lane >> 2);
+      const float *src = O + (int64_t)(row < B ? row : B - 1) * ldO + kc;
+      __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(&sbuf[buf][side][blk * 16 * KC]), 16, 0, 0);
+    }
+  };
+  // operand reads: row m = w*64 + t*16 + lane%16, parameter k = 4 ks + lane/16
+  const int lanem = lane & 15, g = lane >> 4, sw = (lanem >> 2) & 3;
+  const int wm = wave >> 1, wn = wave & 1;
+  int offA[4], offB[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    offA[t] = (wm * 64 + t * 16 + lanem) * KC + g;
+    offB[t] = (wn * 64 + t * 16 + lanem) * KC + g;
+  }
+  // the means of the lane's parameters of chunk c
+  auto means = [&](int c, double (&ob)[4]) {
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int64_t k = (int64_t)c * KC + 4 * ks + g;
+      ob[ks] = obar[k < P ? k : P - 1];
+    }
+  };
+  TT::acc_t acc[4][4];
+  TT::zero(acc);
+  auto chunk = [&](const float *pa, const float *pb, const double (&ob)[4], int64_t k0, auto tail) {
+    constexpr bool TAIL = decltype(tail)::value;
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const int uo = 4 * (ks ^ sw);
+      const bool live = !TAIL || k0 + 4 * ks + g < P;
+      double a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double x = (double)pa[offA[t] + uo] - ob[ks];
+        a[t] = live ? x : 0.0;
+        b[t] = (double)pb[offB[t] + uo] - ob[ks];
+      }
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < 4; ++tn) acc[tm][tn] = TT::mma(a[tm], b[tn], acc[tm][tn]);
+    }
+  };
+  const int nfull = (int)(P / KC), nchunks = (int)((P + KC - 1) / KC);
+  double obc[4], obn[4];
+  means(0, obc);
+  copy(0, 0);
+  for (int c = 0; c < nfull; ++c) {
+    wait_copies();
+    __syncthreads();
+    if (c + 1 < nchunks) {
+      copy(c + 1, (c + 1) & 1);
+      means(c + 1, obn);
+    }
+    chunk(sbuf[c & 1][0], sbuf[c & 1][1], obc, (int64_t)c * KC, std::false_type{});
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) obc[ks] = obn[ks];
+  }
+  if (nfull < nchunks) {
+    wait_copies();
+    __syncthreads();
+    chunk(sbuf[nfull & 1][0], sbuf[nfull & 1][1], obc, (int64_t)nfull * KC, std::true_type{});
+  }
   const double inv = 1.0 / B;
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
@@ -781,10 +873,10 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     const int nt = (int)(T * (T + 1) / 2);
     if (o->s_prec == 1) {
       if (tvec) syrk_dma_kernel<double, SYRK_KC><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
-      else syrk_kernel<double, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      else syrk_kernel<double><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
     } else {
       if (tvec) syrk_dma_kernel<float, SYRK_KC><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
-      else syrk_kernel<float, false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
+      else syrk_kernel<float><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, S, ldS, nt);
     }
     VQMC_LAUNCH_CHECK();
     scale_copy_kernel<<<(unsigned)((P + 255) / 256), 256, 0, st>>>(Fv, P, 1.0, S + P * ldS);
@@ -794,8 +886,8 @@ extern "C" vqmc_status vqmc_sr_solve(const float *O, int64_t ldO, const double *
     double *alpha = reinterpret_cast<double *>(ws + pl.off_alpha);
     const int64_t T = (B + 127) / 128, ldK = ld_even(B);
     const int nt = (int)(T * (T + 1) / 2);
-    if (tvec) gram_kernel<true><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
-    else gram_kernel<false><<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
+    if (tvec) gram_dma_kernel<<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
+    else gram_kernel<<<(unsigned)nt, 256, 0, st>>>(O, ldO, B, P, obar, o->eps, K, ldK, nt);
     scale_copy_kernel<<<(unsigned)((B + 255) / 256), 256, 0, st>>>(ec, B, 1.0 / B, K + B * ldK);
     VQMC_LAUNCH_CHECK();
     rc = chol_factor_solve(K, B, ldK, alpha, ws + pl.off_chol, status, st);
