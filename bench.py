@@ -110,6 +110,28 @@ def sr_opts(V, name):
     }[name]
 
 
+def sr_stage_roofline(sr_name, B, P, ms, iters):
+    """The whole SR stage against the roofline of its arithmetic, from the
+    stage's event time: the explicit S (B P^2 FLOPs for its lower half) plus
+    the Cholesky (P^3 / 3) and the two triangular solves (2 P^2); the
+    sample-space form (B^2 P for the Gram matrix, B^3 / 3, two passes over O);
+    CG by its HBM bytes (two passes over O per iteration)."""
+    t = ms / 1e3
+    if sr_name in ("chol32", "chol64"):
+        flops = B * P * P + P ** 3 / 3 + 2 * P * P
+        scope = "S (B P^2) + Cholesky (P^3/3) + solves (2 P^2) FLOPs over the SR stage time"
+    elif sr_name == "dual":
+        flops = B * B * P + B ** 3 / 3 + 4 * B * P
+        scope = "Gram matrix (B^2 P) + Cholesky (B^3/3) + two passes over O FLOPs over the SR stage time"
+    else:
+        gbs = 2 * B * P * 4 * iters / t / 1e9
+        return {"bound": "hbm", "scope": "two passes over O per CG iteration over the SR stage time",
+                "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK}
+    tf = flops / t / 1e12
+    return {"bound": "mfma", "scope": scope, "flops": flops, "achieved": tf, "peak": PEAK["fp64"],
+            "unit": "TFLOP/s", "frac": tf / PEAK["fp64"]}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -494,7 +516,9 @@ def main():
                          "delta_rel_err": delta_err(d_main),
                          "delta_reference": "sample-space Cholesky, FP64, same O and E",
                          "delta_bar": 1e-3, "meets_delta_bar": delta_err(d_main) <= 1e-3},
-           "roofline": roof, "measured_ceilings": ceil}
+           "roofline": roof,
+           "sr_roofline": sr_stage_roofline(sr_name, B, P, stage[2], sr_info["iters"]),
+           "measured_ceilings": ceil}
     if sampler:
         out["sampler"] = sampler
 
