@@ -28,9 +28,11 @@ def _rel(a, b):
 # last outer panels of several sub-panels ending in a partial one (700, 1700:
 # the fused per-sub-panel launch with fewer than 64 columns), and the next-panel
 # update's 64-row tiles ending in a partial tile (577: 66 rows after the first
-# panel) or exactly (1088: 577 rows, the rest of the trailing matrix one tile)
+# panel) or exactly (1088: 577 rows, the rest of the trailing matrix one tile);
+# the last two put a single partial 128-row tile and a partial last K chunk
+# on the direct-to-LDS S and Gram kernels (P a multiple of 4, B and P not of 16)
 CASES = [(300, 200), (200, 517), (64, 64), (97, 1), (130, 384), (256, 512), (515, 300), (777, 1030),
-         (300, 700), (900, 1700), (300, 577), (640, 1088)]
+         (300, 700), (900, 1700), (300, 577), (640, 1088), (17, 44), (129, 132)]
 
 
 @pytest.mark.parametrize("B,P", CASES)
