@@ -57,6 +57,28 @@ def test_sr_small_parity(B, P, method, s_prec):
 
 
 @pytest.mark.parametrize("method,s_prec", [(V.SR_CHOLESKY, 0), (V.SR_CHOLESKY, 1), (V.SR_DUAL, 1), (V.SR_CG, 1)])
+def test_sr_padded_rows(method, s_prec):
+    """O as a view into wider rows (row stride ldO > P): with 16-byte rows
+    (ldO a multiple of 4) the same kernels run and delta is bit-identical to
+    the contiguous O; with an odd stride the scalar-load forms run and agree
+    to rounding."""
+    B, P = 300, 200
+    O, E = _rand(B, P, 21)
+    Od, Ed = to_dev(O), to_dev(E)
+    announce("sr padded rows", method, s_prec)
+    opts = V.SrOpts(method=method, s_prec=s_prec, eps=1e-3, tol=1e-12, max_iter=500)
+    d0, F0, _ = V.vqmc_sr_solve(Od, Ed, opts)
+    for pad, exact in ((12, True), (1, False)):
+        wide = torch.full((B, P + pad), float("nan"), dtype=torch.float32, device="cuda")
+        wide[:, :P] = Od
+        d1, F1, _ = V.vqmc_sr_solve(wide[:, :P], Ed, opts)
+        if exact:
+            assert torch.equal(d1, d0) and torch.equal(F1, F0), pad
+        else:
+            assert _rel(host(d1), host(d0)) <= 1e-12 and _rel(host(F1), host(F0)) <= 1e-14, pad
+
+
+@pytest.mark.parametrize("method,s_prec", [(V.SR_CHOLESKY, 0), (V.SR_CHOLESKY, 1), (V.SR_DUAL, 1), (V.SR_CG, 1)])
 def test_sr_run_to_run_bit_identical(method, s_prec):
     """Two calls on the same inputs give the same bits: no atomics, fixed
     reduction orders, and at this order (above 1024) the Cholesky's trailing
