@@ -179,6 +179,9 @@ struct LC {
   // rows of both difference buffers together (zero rows included)
   static constexpr int ROWS = ROWS_FIT < 2 * MR + 2 ? ROWS_FIT : 2 * MR + 2;
   static constexpr int SPASS = 2 * FRAGP + ROWS * ROWB;
+  // spill slot of a paired configuration's box of distance 4 (at most 100
+  // rows), whole 1 KiB pieces for the direct-to-LDS copies
+  static constexpr int SPILL_BYTES = (100 * ROWB + 1023) / 1024 * 1024;
   static constexpr int REGION = ((BASE > SPASS ? BASE : SPASS) + 15) / 16 * 16;
   static_assert(REGION + FIXED <= 160 * 1024, "LDS plan exceeds the workgroup's 160 KiB");
   static_assert(FRAGP % 1024 == 0 && FRAG32 % 1024 == 0, "fragment blocks are copied in 1 KiB pieces");
@@ -332,7 +335,7 @@ __device__ __forceinline__ int mod_once(int v, int L) {
   return v >= L ? v - L : v;
 }
 
-template <int C, int PREC, int NW, int TPW>
+template <int C, int PREC, int NW, int TPW, bool PAIRS>
 __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restrict__ theta,
                                                           const char *__restrict__ frag32,
                                                           const char *__restrict__ fragp,
@@ -340,6 +343,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
                                                           int n_layers, double J1, double J2, int marshall,
                                                           int cap_odd, int cap_even,
                                                           float *__restrict__ zscratch,
+                                                          char *__restrict__ spill,
                                                           double *__restrict__ e_loc,
                                                           int32_t *__restrict__ flags,
                                                           double *__restrict__ lp_out) {
@@ -473,10 +477,11 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
     // copied into the other fragment buffer meanwhile.  Each wave leaves its
     // part of the log-ratio in s_dl; thread 0 turns them into terms 16 at a
     // time (in s' order, the waves' parts summed in wave order).
-    // zero rows of both buffers (the dense pass used their room)
-    {
+    // zero rows of the odd buffer (nb = 1) or of both (nb = 2; the dense pass
+    // used their room)
+    auto zero_rows = [&](int nb) {
       const int wb = PREC == P_F32 ? (C + 1) : (PREC == P_X3 ? C : C / 2);  // 32-bit words per zero row
-      for (int idx = tid; idx < 2 * wb; idx += NTHR) {
+      for (int idx = tid; idx < nb * wb; idx += NTHR) {
         const int bsel = idx / wb, w = idx - bsel * wb;
         char *buf = bsel ? s_deven : s_dodd;
         const int cap = bsel ? cap_even : cap_odd;
@@ -491,17 +496,20 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         }
         *p = 0u;
       }
-    }
-    // lift of s' q into the odd buffer: dz_1 = sum_tap W0[c][tap] ds(x + d(tap))
-    // on the box of distance 1, four channels per thread
-    auto lift = [&](int q) {
+    };
+    zero_rows(2);
+    // lift of s' q into the odd buffer at row base: dz_1 = sum_tap W0[c][tap]
+    // ds(x + d(tap)) on the box of distance 1, four channels per item, the
+    // items on threads t0 .. t0 + nthr - 1
+    auto lift = [&](int q, int base, int t0, int nthr) {
+      if (tid < t0 || tid >= t0 + nthr) return;
       int bi, bj, kind, y0, x0, ey, ex;
       pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
       const float dsi = (float)(s_sig[bj] - s_sig[bi]);  // change of spin at bi (at bj: -dsi)
       Box bx;
       bx.set(y0, x0, ey, ex, 1, L);
       const int R = bx.H * bx.W;
-      for (int idx = tid; idx < R * (C / 4); idx += NTHR) {
+      for (int idx = tid - t0; idx < R * (C / 4); idx += nthr) {
         const int r = idx / (C / 4), co0 = 4 * (idx - r * (C / 4));
         const int site = bx.site(r, L), y = site / L, x = site - y * L;
         float dz[4] = {0.f, 0.f, 0.f, 0.f};
@@ -516,7 +524,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         float dh[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) dh[j] = tanh_diff(e[j], dz[j]);
-        dstore4<C, PREC>(s_dodd, cap_odd, r, co0, dh);
+        dstore4<C, PREC>(s_dodd, cap_odd, base + r, co0, dh);
       }
     };
     double eacc = diag;  // thread 0's
@@ -533,113 +541,303 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
         eacc += 0.5 * J * mu * exp(dlog);
       }
     };
-    if (total > 0) lift(0);
-    __syncthreads();
-    int t = 0;  // layers run so far: the current layer's fragments are in buffer t & 1
-    for (int q = 0; q < total; ++q) {
-      int bi, bj, kind, y0, x0, ey, ex;
-      pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
-      // every wave has written its parts of s' q-16 .. q-1 (before a barrier);
-      // the slots written meanwhile (s' q onwards) are the other 16
-      if (tid == 0 && q > 0 && (q & 15) == 0) flush(q, 16);
+    // Pairs (PAIRS): s' q and q + 1 share the steps of layers 1 .. 3, waves
+    // 0 .. NW/2 - 1 on q and the others on q + 1, the second one's boxes at
+    // row offsets so (odd buffer) and se (even buffer); its box of distance 4
+    // goes to a per-workgroup spill slot in global memory, comes back into
+    // the odd buffer by direct-to-LDS copy during the first one's last layer
+    // (n even: the odd buffer is free then) and is moved into the even
+    // buffer before its own layers 4 .. n (that copy may cover the odd
+    // buffer's zero rows: they are cleared again).
+    const int so = box_rows_max(3, L), se = box_rows_max(2, L);
+    char *spl = PAIRS ? spill + (size_t)blockIdx.x * K::SPILL_BYTES : nullptr;
+    auto lift_next = [&](int qn) {
+      if (PAIRS && qn + 1 < total) {
+        lift(qn, 0, 0, NTHR / 2);
+        lift(qn + 1, so, NTHR / 2, NTHR / 2);
+      } else {
+        lift(qn, 0, 0, NTHR);
+      }
+    };
+    struct PB {
+      int y0, x0, ey, ex;
+    };
+    auto pbox = [&](int q) {
+      PB p;
+      int bi, bj, kind;
+      pair_box(s_bonds[q], L, N, bi, bj, kind, p.y0, p.x0, p.ey, p.ex);
+      return p;
+    };
+    int t = 0;  // layer steps run so far: the current step's fragments are in buffer t & 1
+    // One layer step: layer l of the s' whose box is pa (HALF = 0, every
+    // wave), or of the pair pa, pb (HALF = 1, l <= 3); the fragments of layer
+    // fidx + 1 are copied meanwhile (fidx < 0: none).  Returns the wave's part
+    // of the log-ratio at the last layer.
+    auto step = [&](auto half_c, int l, const PB &pa, const PB &pb, int fidx) {
+      constexpr bool HALF = decltype(half_c)::value;
+      constexpr int NWS = HALF ? NW / 2 : NW;
+      const int hb = HALF ? (wave >= NW / 2 ? 1 : 0) : 0;
+      const int wv = wave - hb * (NW / 2);
+      const PB &pq = hb ? pb : pa;
+      const int in_base = hb ? ((l & 1) ? so : se) : 0;
+      const int out_base = hb ? ((l & 1) ? se : so) : 0;
+      const bool to_spill = HALF && hb && l == 3;
       double part = 0.0;
-      for (int l = 1; l <= n_layers; ++l) {
-        const char *din = (l & 1) ? s_dodd : s_deven;
-        const int cap_in = (l & 1) ? cap_odd : cap_even;
-        char *dout = (l & 1) ? s_deven : s_dodd;
-        const int cap_out = (l & 1) ? cap_even : cap_odd;
-        Box bo, bn;
-        bn.set(y0, x0, ey, ex, l, L);      // input box
-        bo.set(y0, x0, ey, ex, l + 1, L);  // output box
-        const int R = bo.H * bo.W;
-        // tiles of this wave in the output box (wave-uniform)
-        const int Ttot = (R + 15) / 16;
-        const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
-        // the lane's output row in tile slot i (rows past the box repeat the
-        // last one and are not stored): its lattice site, and the rows of
-        // the input box that its 3x3 neighbourhood reads
-        const float *zl = zsc + (size_t)l * N * C;
-        const char *fcur = s_region + (t & 1) * K::FRAGP;
-        // the next layer's fragments (after the last layer: the first one's,
-        // for the next s') go into the other buffer, read last by the
-        // previous layer
-        const bool copy_next = l < n_layers || q + 1 < total;
-        char *fnext = s_region + ((t + 1) & 1) * K::FRAGP;
-        const char *fsrc = fragp + (size_t)(l < n_layers ? l : 0) * K::FRAGP;
-        // One compile-time body per tile count of this wave: the loaded
-        // exponentials are used only inside it (a register copy at a branch
-        // merge would wait for them, and for the fragment copy issued after
-        // them, before the K loop).
-        auto body = [&](auto ntile) {
-          constexpr int NTILE = decltype(ntile)::value;
-          // the lane's output row in tile slot i (rows past the box repeat
-          // the last one and are not stored): its lattice site, and the rows
-          // of the input box that its 3x3 neighbourhood reads
-          int site[TPW], ro[TPW][3], cf[TPW][3];
+      const char *din = (l & 1) ? s_dodd : s_deven;
+      const int cap_in = (l & 1) ? cap_odd : cap_even;
+      char *dout = (l & 1) ? s_deven : s_dodd;
+      const int cap_out = (l & 1) ? cap_even : cap_odd;
+      Box bo, bn;
+      bn.set(pq.y0, pq.x0, pq.ey, pq.ex, l, L);      // input box
+      bo.set(pq.y0, pq.x0, pq.ey, pq.ex, l + 1, L);  // output box
+      const int R = bo.H * bo.W;
+      // tiles of this wave in the output box (wave-uniform)
+      const int Ttot = (R + 15) / 16;
+      const int nti = Ttot > wv ? (Ttot - wv + NWS - 1) / NWS : 0;
+      const float *zl = zsc + (size_t)l * N * C;
+      const char *fcur = s_region + (t & 1) * K::FRAGP;
+      // the next step's fragments go into the other buffer, read last by the
+      // previous step
+      const bool copy_next = fidx >= 0;
+      char *fnext = s_region + ((t + 1) & 1) * K::FRAGP;
+      const char *fsrc = fragp + (size_t)(copy_next ? fidx : 0) * K::FRAGP;
+      // One compile-time body per tile count of this wave: the loaded
+      // exponentials are used only inside it (a register copy at a branch
+      // merge would wait for them, and for the fragment copy issued after
+      // them, before the K loop).
+      auto body = [&](auto ntile) {
+        constexpr int NTILE = decltype(ntile)::value;
+        // the lane's output row in tile slot i (rows past the box repeat
+        // the last one and are not stored): its lattice site, and the rows
+        // of the input box that its 3x3 neighbourhood reads
+        int site[TPW], ro[TPW][3], cf[TPW][3];
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i) {
+          int r = (wv + i * NWS) * 16 + (lane & 15);
+          r = r < R ? r : R - 1;
+          const int ry = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)bo.W)), rx = r - ry * bo.W;
+          const int y = mod_once(bo.ys + ry, L), x = mod_once(bo.xs + rx, L);
+          site[i] = y * L + x;
+          const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            int vy = ay + d - 1, vx = ax + d - 1;
+            vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
+            vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
+            ro[i][d] = vy < bn.H ? in_base + vy * bn.W : -(1 << 20);
+            cf[i][d] = vx < bn.W ? vx : -(1 << 20);
+          }
+        }
+        // the stored e^{2 z_l(s)} of the lane's rows, requested before the
+        // K loop so that the matrix work covers the memory latency
+        f32x4 za[TPW][NT];
+#pragma unroll
+        for (int i = 0; i < NTILE; ++i)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            za[i][nt] = *reinterpret_cast<const f32x4 *>(zl + site[i] * C + nt * 16 + 4 * (lane >> 4));
+        if (copy_next) stage_async_fixed<NW, K::FRAGP>(fnext, fsrc);
+        if constexpr (NTILE > 0) {
+          f32x4 acc[TPW][NT];
+          kloop_box<C, PREC, TPW, NTILE>(din, cap_in, fcur, ro, cf, acc);
 #pragma unroll
           for (int i = 0; i < NTILE; ++i) {
-            int r = (wave + i * NW) * 16 + (lane & 15);
-            r = r < R ? r : R - 1;
-            const int ry = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)bo.W)), rx = r - ry * bo.W;
-            const int y = mod_once(bo.ys + ry, L), x = mod_once(bo.xs + rx, L);
-            site[i] = y * L + x;
-            const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
+            const int r = (wv + i * NWS) * 16 + (lane & 15);
+            if (r < R) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              int vy = ay + d - 1, vx = ax + d - 1;
-              vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
-              vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
-              ro[i][d] = vy < bn.H ? vy * bn.W : -(1 << 20);
-              cf[i][d] = vx < bn.W ? vx : -(1 << 20);
-            }
-          }
-          // the stored e^{2 z_l(s)} of the lane's rows, requested before the
-          // K loop so that the matrix work covers the memory latency
-          f32x4 za[TPW][NT];
+              for (int nt = 0; nt < NT; ++nt) {
+                float dh[4];
 #pragma unroll
-          for (int i = 0; i < NTILE; ++i)
+                for (int jj = 0; jj < 4; ++jj) dh[jj] = tanh_diff(za[i][nt][jj], acc[i][nt][jj]);
+                if (HALF || l < n_layers) {
+                  if (to_spill) dstore4<C, PREC>(spl, R - 1, r, nt * 16 + 4 * (lane >> 4), dh);
+                  else dstore4<C, PREC>(dout, cap_out, out_base + r, nt * 16 + 4 * (lane >> 4), dh);
+                } else {
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-              za[i][nt] = *reinterpret_cast<const f32x4 *>(zl + site[i] * C + nt * 16 + 4 * (lane >> 4));
-          if (copy_next) stage_async_fixed<NW, K::FRAGP>(fnext, fsrc);
-          if constexpr (NTILE > 0) {
-            f32x4 acc[TPW][NT];
-            kloop_box<C, PREC, TPW, NTILE>(din, cap_in, fcur, ro, cf, acc);
-#pragma unroll
-            for (int i = 0; i < NTILE; ++i) {
-              const int r = (wave + i * NW) * 16 + (lane & 15);
-              if (r < R) {
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                  float dh[4];
-#pragma unroll
-                  for (int jj = 0; jj < 4; ++jj) dh[jj] = tanh_diff(za[i][nt][jj], acc[i][nt][jj]);
-                  if (l < n_layers) {
-                    dstore4<C, PREC>(dout, cap_out, r, nt * 16 + 4 * (lane >> 4), dh);
-                  } else {
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) part += (double)dh[jj];
-                  }
+                  for (int jj = 0; jj < 4; ++jj) part += (double)dh[jj];
                 }
               }
             }
           }
-        };
-        with_tiles<TPW>(nti, body);
-        if (l == n_layers) {
-          part = wave_sum(part);
-          if (lane == 0) s_dl[(q & (K::SLOTS - 1)) * NW + wave] = part;
-          // with n even the last layer reads the even buffer: the next s'
-          // lift fills the odd one now
-          if (!(n_layers & 1) && q + 1 < total) lift(q + 1);
         }
-        wait_copies();
-        __syncthreads();
-        ++t;
+      };
+      // a pair's boxes (at most 100 rows, 7 tiles) give each of the NW / 2
+      // waves of a configuration at most two tiles
+      with_tiles<(HALF && TPW > 2) ? 2 : TPW>(nti, body);
+      return part;
+    };
+    if (total > 0) lift_next(0);
+    __syncthreads();
+    if constexpr (!PAIRS) {
+      // one s' at a time (kept apart from the paired form's step code, which
+      // the compiler schedules differently)
+      for (int q = 0; q < total; ++q) {
+        int bi, bj, kind, y0, x0, ey, ex;
+        pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
+        // every wave has written its parts of s' q-16 .. q-1 (before a barrier);
+        // the slots written meanwhile (s' q onwards) are the other 16
+        if (tid == 0 && q > 0 && (q & 15) == 0) flush(q, 16);
+        double part = 0.0;
+        for (int l = 1; l <= n_layers; ++l) {
+          const char *din = (l & 1) ? s_dodd : s_deven;
+          const int cap_in = (l & 1) ? cap_odd : cap_even;
+          char *dout = (l & 1) ? s_deven : s_dodd;
+          const int cap_out = (l & 1) ? cap_even : cap_odd;
+          Box bo, bn;
+          bn.set(y0, x0, ey, ex, l, L);      // input box
+          bo.set(y0, x0, ey, ex, l + 1, L);  // output box
+          const int R = bo.H * bo.W;
+          // tiles of this wave in the output box (wave-uniform)
+          const int Ttot = (R + 15) / 16;
+          const int nti = Ttot > wave ? (Ttot - wave + NW - 1) / NW : 0;
+          // the lane's output row in tile slot i (rows past the box repeat the
+          // last one and are not stored): its lattice site, and the rows of
+          // the input box that its 3x3 neighbourhood reads
+          const float *zl = zsc + (size_t)l * N * C;
+          const char *fcur = s_region + (t & 1) * K::FRAGP;
+          // the next layer's fragments (after the last layer: the first one's,
+          // for the next s') go into the other buffer, read last by the
+          // previous layer
+          const bool copy_next = l < n_layers || q + 1 < total;
+          char *fnext = s_region + ((t + 1) & 1) * K::FRAGP;
+          const char *fsrc = fragp + (size_t)(l < n_layers ? l : 0) * K::FRAGP;
+          // One compile-time body per tile count of this wave: the loaded
+          // exponentials are used only inside it (a register copy at a branch
+          // merge would wait for them, and for the fragment copy issued after
+          // them, before the K loop).
+          auto body = [&](auto ntile) {
+            constexpr int NTILE = decltype(ntile)::value;
+            // the lane's output row in tile slot i (rows past the box repeat
+            // the last one and are not stored): its lattice site, and the rows
+            // of the input box that its 3x3 neighbourhood reads
+            int site[TPW], ro[TPW][3], cf[TPW][3];
+  #pragma unroll
+            for (int i = 0; i < NTILE; ++i) {
+              int r = (wave + i * NW) * 16 + (lane & 15);
+              r = r < R ? r : R - 1;
+              const int ry = (int)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)bo.W)), rx = r - ry * bo.W;
+              const int y = mod_once(bo.ys + ry, L), x = mod_once(bo.xs + rx, L);
+              site[i] = y * L + x;
+              const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
+  #pragma unroll
+              for (int d = 0; d < 3; ++d) {
+                int vy = ay + d - 1, vx = ax + d - 1;
+                vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
+                vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
+                ro[i][d] = vy < bn.H ? vy * bn.W : -(1 << 20);
+                cf[i][d] = vx < bn.W ? vx : -(1 << 20);
+              }
+            }
+            // the stored e^{2 z_l(s)} of the lane's rows, requested before the
+            // K loop so that the matrix work covers the memory latency
+            f32x4 za[TPW][NT];
+  #pragma unroll
+            for (int i = 0; i < NTILE; ++i)
+  #pragma unroll
+              for (int nt = 0; nt < NT; ++nt)
+                za[i][nt] = *reinterpret_cast<const f32x4 *>(zl + site[i] * C + nt * 16 + 4 * (lane >> 4));
+            if (copy_next) stage_async_fixed<NW, K::FRAGP>(fnext, fsrc);
+            if constexpr (NTILE > 0) {
+              f32x4 acc[TPW][NT];
+              kloop_box<C, PREC, TPW, NTILE>(din, cap_in, fcur, ro, cf, acc);
+  #pragma unroll
+              for (int i = 0; i < NTILE; ++i) {
+                const int r = (wave + i * NW) * 16 + (lane & 15);
+                if (r < R) {
+  #pragma unroll
+                  for (int nt = 0; nt < NT; ++nt) {
+                    float dh[4];
+  #pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) dh[jj] = tanh_diff(za[i][nt][jj], acc[i][nt][jj]);
+                    if (l < n_layers) {
+                      dstore4<C, PREC>(dout, cap_out, r, nt * 16 + 4 * (lane >> 4), dh);
+                    } else {
+  #pragma unroll
+                      for (int jj = 0; jj < 4; ++jj) part += (double)dh[jj];
+                    }
+                  }
+                }
+              }
+            }
+          };
+          with_tiles<TPW>(nti, body);
+          if (l == n_layers) {
+            part = wave_sum(part);
+            if (lane == 0) s_dl[(q & (K::SLOTS - 1)) * NW + wave] = part;
+            // with n even the last layer reads the even buffer: the next s'
+            // lift fills the odd one now
+            if (!(n_layers & 1) && q + 1 < total) lift(q + 1, 0, 0, NTHR);
+          }
+          wait_copies();
+          __syncthreads();
+          ++t;
+        }
+        if ((n_layers & 1) && q + 1 < total) {
+          lift(q + 1, 0, 0, NTHR);
+          __syncthreads();
+        }
       }
-      if ((n_layers & 1) && q + 1 < total) {
-        lift(q + 1);
-        __syncthreads();
+    } else {
+      for (int q = 0; q < total;) {
+        // every wave has written its parts of s' q-16 .. q-1 (before a barrier);
+        // the slots written meanwhile (s' q onwards) are the other 16
+        if (tid == 0 && q > 0 && (q & 15) == 0) flush(q, 16);
+        const bool pr = PAIRS && q + 1 < total;
+        const int qn = q + (pr ? 2 : 1);  // the next unit's first s'
+        const PB pa = pbox(q), pb = pr ? pbox(q + 1) : pa;
+        // steps: the pair's layers 1 .. 3, then layers 4 .. n of q and of q + 1;
+        // or layers 1 .. n of q alone
+        const int nsteps = pr ? 2 * n_layers - 3 : n_layers;
+        for (int st = 0; st < nsteps; ++st) {
+          if (pr && st < 3) {
+            step(IntC<1>{}, st + 1, pa, pb, st + 1);
+          } else {
+            const int second = pr && st >= n_layers;  // s' q + 1 of a pair
+            const int l = second ? st - n_layers + 4 : st + 1;
+            const int fidx = l < n_layers ? l : ((pr && !second) ? 3 : (qn < total ? 0 : -1));
+            // the first of a pair's last layer: its partner's spilled box comes
+            // back into the odd buffer (issued before this step's loads, so
+            // that their waits are not lengthened by it; the K loop covers it)
+            if (pr && !second && l == n_layers) stage_async_fixed<NW, K::SPILL_BYTES>(s_dodd, spl);
+            double part = step(IntC<0>{}, l, second ? pb : pa, pb, fidx);
+            if (l == n_layers) {
+              part = wave_sum(part);
+              if (lane == 0) s_dl[((q + second) & (K::SLOTS - 1)) * NW + wave] = part;
+              // with n even the last layer reads the even buffer: the next
+              // lift fills the odd one now (for the first of a pair: the copy
+              // above does)
+              if (!(n_layers & 1) && !(pr && !second) && qn < total) lift_next(qn);
+            }
+          }
+          wait_copies();
+          __syncthreads();
+          ++t;
+          if (pr && st == n_layers - 1) {
+            // the partner's box of distance 4: odd buffer -> even rows 0 .. R4 - 1
+            Box b4;
+            b4.set(pb.y0, pb.x0, pb.ey, pb.ex, 4, L);
+            const int R4 = b4.H * b4.W;
+            if constexpr (PREC == P_F32) {
+              const uint32_t *src = reinterpret_cast<const uint32_t *>(s_dodd);
+              uint32_t *dst = reinterpret_cast<uint32_t *>(s_deven);
+              for (int w = tid; w < R4 * (C + 1); w += NTHR) dst[w] = src[w];
+            } else {
+              const int pw = R4 * C / 8;  // 16-byte pieces per plane
+              for (int w = tid; w < (PREC == P_X3 ? 2 : 1) * pw; w += NTHR) {
+                const int pl = w >= pw ? 1 : 0, o = w - pl * pw;
+                const uint4 v = *reinterpret_cast<const uint4 *>(s_dodd + (size_t)pl * R4 * C * 2 + o * 16);
+                *reinterpret_cast<uint4 *>(s_deven + (size_t)pl * (cap_even + 1) * C * 2 + o * 16) = v;
+              }
+            }
+            __syncthreads();
+            zero_rows(1);
+          }
+        }
+        if ((n_layers & 1) && qn < total) {
+          lift_next(qn);
+          __syncthreads();
+        }
+        q = qn;
       }
     }
     if (tid == 0) {
@@ -652,6 +850,21 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
 }
 
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Whether two s' can share the first three layer steps (see the kernel):
+// twelve waves, n even and at least 4, both configurations' boxes of
+// distance 1 .. 3 side by side in the buffers, a box of distance 4 in the
+// even one, and the spill slot's copy within the odd buffer.
+template <int C, int PREC, int NW, int TPW>
+bool lc_pairs(int L, int n) {
+  using K = LC<C, PREC, NW, TPW>;
+  if (NW != 12 || (n & 1) || n < 4) return false;
+  int cap_odd, cap_even;
+  lc_caps(n, L, cap_odd, cap_even);
+  return 2 * box_rows_max(3, L) <= cap_odd && 2 * box_rows_max(2, L) <= cap_even &&
+         (box_rows_max(4, L) + 15) / 16 <= 2 * (NW / 2) && box_rows_max(4, L) <= cap_even &&
+         box_rows_max(4, L) * K::ROWB <= K::SPILL_BYTES && K::SPILL_BYTES <= (cap_odd + 1) * K::ROWB;
+}
 
 template <int C, int PREC, int NW, int TPW>
 bool lc_fits(int L, int n) {
@@ -690,11 +903,23 @@ int lc_grid_c(int N, int B) {
 }
 
 template <int C, int PREC>
+int lc_spill_c(int N) {
+  switch (lc_shape(N)) {
+    case 0: return LC<C, PREC, 4, 1>::SPILL_BYTES;
+    case 1: return LC<C, PREC, 4, 2>::SPILL_BYTES;
+    case 2: return LC<C, PREC, 12, 2>::SPILL_BYTES;
+    default: return LC<C, PREC, 12, 3>::SPILL_BYTES;
+  }
+}
+
+// packed FP32 fragments | packed fragments of the difference pass | per
+// workgroup: the stored exponentials of s, then a spill slot
+template <int C, int PREC>
 size_t lc_ws(const vqmc_model *m, int B) {
   const int N = m->L * m->L, n = m->n_layers;
   const int grid = B > 0 ? lc_grid_c<C, PREC>(N, B) : 0;
   return al256(n * frag_bytes_per_layer<C, P_F32>()) + al256(n * frag_bytes_per_layer<C, PREC>()) +
-         (size_t)grid * (n + 1) * N * C * 4;
+         al256((size_t)grid * (n + 1) * N * C * 4) + (size_t)grid * lc_spill_c<C, PREC>(N);
 }
 
 template <int C, int PREC, int NW, int TPW>
@@ -709,13 +934,21 @@ vqmc_status lc_launch(const vqmc_model *m, const float *theta, const int8_t *spi
   char *f32 = ws;
   char *fp = ws + al256(n * frag_bytes_per_layer<C, P_F32>());
   float *z = reinterpret_cast<float *>(fp + al256(n * frag_bytes_per_layer<C, PREC>()));
+  const int grid = lc_grid<C, PREC, NW, TPW>(B);
+  char *spill = reinterpret_cast<char *>(z) + al256((size_t)grid * (n + 1) * m->L * m->L * C * 4);
   const int t32 = n * Engine<C, P_F32, 1, 1>::KS * Engine<C, P_F32, 1, 1>::NT * 64;
   const int tp = n * Engine<C, PREC, 1, 1>::KS * Engine<C, PREC, 1, 1>::NT * 64;
   pack_layer_frags_kernel<C, P_F32><<<(t32 + 255) / 256, 256, 0, st>>>(theta, n, f32);
   if (PREC != P_F32) pack_layer_frags_kernel<C, PREC><<<(tp + 255) / 256, 256, 0, st>>>(theta, n, fp);
   else fp = f32;
-  eloc_lc_kernel<C, PREC, NW, TPW><<<lc_grid<C, PREC, NW, TPW>(B), NW * 64, 0, st>>>(
-      theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, cap_odd, cap_even, z, e_loc, flags, lp);
+  // the paired form is a kernel of its own, so that the plain one keeps its
+  // registers
+  if (NW == 12 && lc_pairs<C, PREC, NW, TPW>(m->L, n))
+    eloc_lc_kernel<C, PREC, NW, TPW, true><<<grid, NW * 64, 0, st>>>(
+        theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, cap_odd, cap_even, z, spill, e_loc, flags, lp);
+  else
+    eloc_lc_kernel<C, PREC, NW, TPW, false><<<grid, NW * 64, 0, st>>>(
+        theta, f32, fp, spins, B, m->L, n, m->J1, m->J2, m->marshall, cap_odd, cap_even, z, spill, e_loc, flags, lp);
   if (hipGetLastError() != hipSuccess) return VQMC_ERR_DEVICE;
   return VQMC_OK;
 }
