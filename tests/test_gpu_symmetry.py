@@ -123,9 +123,19 @@ def test_sym_local_energy_lightcone(prec):
     _sym_eloc(8, 16, 3, 6, prec, V.ELOC_LIGHTCONE, tol_each=tol[0], tol_mean=tol[1])
 
 
+@pytest.mark.parametrize("prec", [V.PREC_FP32, V.PREC_BF16X3])
+def test_sym_local_energy_lightcone_16x16(prec):
+    # 16x16, C = 32, eight layers: the form of the light cone in which two
+    # exchanged configurations share the first three layer steps, here over
+    # the four rotations of each configuration (FP32 bars scaled by
+    # sqrt(N C) as for the unsymmetrised 16x16 energies)
+    tol = (1e-4, 5e-5) if prec == V.PREC_FP32 else (1e-3, 1e-4)
+    _sym_eloc(16, 32, 8, 2, prec, V.ELOC_LIGHTCONE, tol_each=tol[0], tol_mean=tol[1])
+
+
 def test_sym_local_energy_lightcone_vs_dense_16x16():
-    """Both GPU methods at 16x16, C = 32, eight layers (too large for the
-    oracle's symmetrised energy), and the rotation invariance of each."""
+    """Both GPU methods at 16x16, C = 32, eight layers on three more
+    configurations, and the rotation invariance of each."""
     th = to_dev(init_theta(32, 8, seed=0))
     s = uniform_sz0(16, 3, seed=3)
     res = {}
