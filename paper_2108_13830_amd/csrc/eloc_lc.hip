@@ -254,7 +254,7 @@ __device__ __forceinline__ void kloop_box(const char *in, int cap, const char *f
 #pragma unroll
       for (int i = 0; i < NTILE; ++i) {
         const int g = sel3(ro[i], dy) + sel3(cf[i], dx);
-        nb[i] = (g < 0 ? cap : g) * (C + 1);
+        nb[i] = (int)min((unsigned)g, (unsigned)cap) * (C + 1);  // outside the box: the zero row
       }
 #pragma unroll
       for (int c4 = 0; c4 < SPT; ++c4) {
@@ -293,8 +293,10 @@ __device__ __forceinline__ void kloop_box(const char *in, int cap, const char *f
       u16x8 ah[NTILE], al[NTILE];
 #pragma unroll
       for (int i = 0; i < NTILE; ++i) {
+        // a negative index (outside the box) is huge as unsigned: the minimum
+        // with cap picks the zero row; rows of the box lie below cap
         const int g = sel3(ro[i], dy) + sel3(cf[i], dx);
-        const int p = E::phys(g < 0 ? cap : g, ci0);
+        const int p = E::phys((int)min((unsigned)g, (unsigned)cap), ci0);
         ah[i] = *reinterpret_cast<const u16x8 *>(hi + p);
         if constexpr (PREC == P_X3) al[i] = *reinterpret_cast<const u16x8 *>(lo + p);
       }
