@@ -70,6 +70,25 @@ def test_lightcone_edge_configs_and_couplings():
         _check(gm, rm, th, s, 1e-5, 1e-4)
 
 
+def test_lightcone_paired_edge_configs():
+    # 16x16, n = 8: the paired form (two exchanged configurations per layer
+    # step for layers 1 .. 3) on Neel (every J1 bond antiparallel: 512
+    # exchanged configurations) and on a half-up / half-down configuration (96)
+    L, C, n = 16, 32, 8
+    th = init_theta(C, n, seed=4)
+    s = np.concatenate([neel(L, 1), ferro_like_sz0(L)])
+    for prec in (V.PREC_FP32, V.PREC_BF16X3):
+        gm, rm = _lc(L, C, n, prec)
+        _check(gm, rm, th, s, *TOL[prec])
+    # all spins up: no exchanged configuration, the diagonal term alone (4N
+    # bonds with s_i s_j = 1: N (2 J1 + 2 J2) / 4), flagged as Sz != 0
+    gm, _ = _lc(L, C, n, V.PREC_FP32)
+    flags = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    e = host(V.vqmc_local_energy(gm, to_dev(th), to_dev(np.ones((1, L * L), np.int8)), flags=flags))
+    assert e[0] == L * L * (2 * 1.0 + 2 * 0.5) / 4
+    assert host(flags)[0] == 2
+
+
 def test_lightcone_matches_dense_and_zero_params():
     gm, _ = _lc(10, 16, 6, V.PREC_FP32)
     th = to_dev(init_theta(16, 6, seed=0))
