@@ -90,19 +90,21 @@ __device__ __forceinline__ float exp2x(float a) { return __expf(2.f * fminf(fmax
 // and capped at 1e30: beyond it tanh(a + b) = 1 in FP32.  Where the
 // denominator overflows (E_a > 3e8 with E_c capped) the result is 0, within
 // 1e-8 of the exact 2 / (E_a + 1).  One exponential (the hardware 2^x of
-// 2b log2 e) and one reciprocal.
+// 2b log2 e) and one reciprocal.  The factors 2 are folded in exactly (powers
+// of two scale without rounding): the series gives 2 s(b), and the
+// denominator is (E_c + 1)(E_a + 1) / 2.
 __device__ __forceinline__ float tanh_diff(float ea, float b) {
   const float e = __builtin_amdgcn_exp2f(fminf(b * 2.8853900817779268f, 126.f));
   const float ec = fminf(ea * e, 1e30f);
-  const float sb =
-      b * (1.f + b * (1.f + b * (2.f / 3.f + b * (1.f / 3.f + b * (2.f / 15.f + b * (2.f / 45.f))))));
+  const float sb2 =
+      b * (2.f + b * (2.f + b * (4.f / 3.f + b * (2.f / 3.f + b * (4.f / 15.f + b * (4.f / 45.f))))));
   // both candidates are formed and one is picked bitwise (a conditional
   // expression here compiles to a branch per element)
   const int sel = -(int)(fabsf(b) < 0.125f);
-  const int u = __float_as_int(2.f * ea * sb), t = __float_as_int(ec - ea);
+  const int u = __float_as_int(ea * sb2), t = __float_as_int(ec - ea);
   const float num = __int_as_float(t ^ ((t ^ u) & sel));
-  const float ea1 = ea + 1.f;
-  return 2.f * num * __builtin_amdgcn_rcpf(fmaf(ec, ea1, ea1));
+  const float h = fmaf(ea, 0.5f, 0.5f);  // (E_a + 1) / 2
+  return num * __builtin_amdgcn_rcpf(fmaf(ec, h, h));
 }
 
 // Unwrapped bounding box of the exchanged pair of bond k: rows y0..y0+ey,
