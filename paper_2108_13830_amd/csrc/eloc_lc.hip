@@ -510,19 +510,27 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
       int bi, bj, kind, y0, x0, ey, ex;
       pair_box(s_bonds[q], L, N, bi, bj, kind, y0, x0, ey, ex);
       const float dsi = (float)(s_sig[bj] - s_sig[bi]);  // change of spin at bi (at bj: -dsi)
+      const int yi = bi / L, xi = bi - yi * L, yj = bj / L, xj = bj - yj * L;
       Box bx;
       bx.set(y0, x0, ey, ex, 1, L);
       const int R = bx.H * bx.W;
       for (int idx = tid - t0; idx < R * (C / 4); idx += nthr) {
         const int r = idx / (C / 4), co0 = 4 * (idx - r * (C / 4));
         const int site = bx.site(r, L), y = site / L, x = site - y * L;
-        float dz[4] = {0.f, 0.f, 0.f, 0.f};
+        // bi and bj each enter through one tap of x at most (L >= 4: the nine
+        // taps of a site are nine distinct sites): tap (ty, tx), ty = (y_b -
+        // y + 1) mod L, tx likewise, when both are at most 2
+        const int tyi = mod_once(yi - y + 1, L), txi = mod_once(xi - x + 1, L);
+        const int tyj = mod_once(yj - y + 1, L), txj = mod_once(xj - x + 1, L);
+        const bool hi_ = tyi <= 2 && txi <= 2, hj = tyj <= 2 && txj <= 2;
+        const int ti = hi_ ? 3 * tyi + txi : 0, tj = hj ? 3 * tyj + txj : 0;
+        float dz[4];
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-          const int nb = wrapL(y + tap / 3 - 1, L) * L + wrapL(x + tap % 3 - 1, L);
-          const float d = nb == bi ? dsi : (nb == bj ? -dsi : 0.f);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) dz[j] += theta[(co0 + j) * 9 + tap] * d;
+        for (int j = 0; j < 4; ++j) {
+          const float wi = hi_ ? theta[(co0 + j) * 9 + ti] : 0.f, wj = hj ? theta[(co0 + j) * 9 + tj] : 0.f;
+          // the sum of the nine taps' terms (the other seven are zero); + 0
+          // keeps a row that neither site reaches at +0
+          dz[j] = fmaf(wj, -dsi, wi * dsi) + 0.f;
         }
         const f32x4 e = *reinterpret_cast<const f32x4 *>(zsc + site * C + co0);
         float dh[4];
