@@ -633,9 +633,16 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
           const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
+            // ay, ax lie in [0, L): only the neighbour above (left) can
+            // wrap, to L - 1, and only the one below (right), to 0
             int vy = ay + d - 1, vx = ax + d - 1;
-            vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
-            vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
+            if (d == 0) {
+              vy = vy < 0 ? L - 1 : vy;
+              vx = vx < 0 ? L - 1 : vx;
+            } else if (d == 2) {
+              vy = vy >= L ? 0 : vy;
+              vx = vx >= L ? 0 : vx;
+            }
             ro[i][d] = vy < bn.H ? in_base + vy * bn.W : -(1 << 20);
             cf[i][d] = vx < bn.W ? vx : -(1 << 20);
           }
@@ -733,9 +740,16 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
               const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
   #pragma unroll
               for (int d = 0; d < 3; ++d) {
+                // ay, ax lie in [0, L): only the neighbour above (left) can
+                // wrap, to L - 1, and only the one below (right), to 0
                 int vy = ay + d - 1, vx = ax + d - 1;
-                vy = vy < 0 ? L - 1 : (vy >= L ? 0 : vy);
-                vx = vx < 0 ? L - 1 : (vx >= L ? 0 : vx);
+                if (d == 0) {
+                  vy = vy < 0 ? L - 1 : vy;
+                  vx = vx < 0 ? L - 1 : vx;
+                } else if (d == 2) {
+                  vy = vy >= L ? 0 : vy;
+                  vx = vx >= L ? 0 : vx;
+                }
                 ro[i][d] = vy < bn.H ? vy * bn.W : -(1 << 20);
                 cf[i][d] = vx < bn.W ? vx : -(1 << 20);
               }
