@@ -730,7 +730,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
             // the last one and are not stored): its lattice site, and the rows
             // of the input box that its 3x3 neighbourhood reads
             int site[TPW], ro[TPW][3], cf[TPW][3];
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < NTILE; ++i) {
               int r = (wave + i * NW) * 16 + (lane & 15);
               r = r < R ? r : R - 1;
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
               const int y = mod_once(bo.ys + ry, L), x = mod_once(bo.xs + rx, L);
               site[i] = y * L + x;
               const int ay = mod_once(y - bn.ys, L), ax = mod_once(x - bn.xs, L);
-  #pragma unroll
+#pragma unroll
               for (int d = 0; d < 3; ++d) {
                 // ay, ax lie in [0, L): only the neighbour above (left) can
                 // wrap, to L - 1, and only the one below (right), to 0
@@ -757,28 +757,28 @@ __global__ __launch_bounds__(NW * 64) void eloc_lc_kernel(const float *__restric
             // the stored e^{2 z_l(s)} of the lane's rows, requested before the
             // K loop so that the matrix work covers the memory latency
             f32x4 za[TPW][NT];
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < NTILE; ++i)
-  #pragma unroll
+#pragma unroll
               for (int nt = 0; nt < NT; ++nt)
                 za[i][nt] = *reinterpret_cast<const f32x4 *>(zl + site[i] * C + nt * 16 + 4 * (lane >> 4));
             if (copy_next) stage_async_fixed<NW, K::FRAGP>(fnext, fsrc);
             if constexpr (NTILE > 0) {
               f32x4 acc[TPW][NT];
               kloop_box<C, PREC, TPW, NTILE>(din, cap_in, fcur, ro, cf, acc);
-  #pragma unroll
+#pragma unroll
               for (int i = 0; i < NTILE; ++i) {
                 const int r = (wave + i * NW) * 16 + (lane & 15);
                 if (r < R) {
-  #pragma unroll
+#pragma unroll
                   for (int nt = 0; nt < NT; ++nt) {
                     float dh[4];
-  #pragma unroll
+#pragma unroll
                     for (int jj = 0; jj < 4; ++jj) dh[jj] = tanh_diff(za[i][nt][jj], acc[i][nt][jj]);
                     if (l < n_layers) {
                       dstore4<C, PREC>(dout, cap_out, r, nt * 16 + 4 * (lane >> 4), dh);
                     } else {
-  #pragma unroll
+#pragma unroll
                       for (int jj = 0; jj < 4; ++jj) part += (double)dh[jj];
                     }
                   }
