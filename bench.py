@@ -48,12 +48,14 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
     convolution rows of the pair's neighbourhood at that distance.
 
     Executed: the products the matrix cores run in the convolution precision,
-    counted as the kernels issue them.  Dense: every batch of G = rows / N
-    configurations runs all rows of the workgroup (448 in the C = 16 BF16
-    forms at up to 448 sites, else 512 at C <= 16 and 576 at C = 32), with K
-    padded to whole instruction steps (4 for FP32, 32 for BF16: 144 -> 160 at
-    C = 16), plus, for FP32, the 1 -> C lift (K = 9 padded to 12; in the BF16
-    forms the lift runs on the FP32 matrix cores and is not counted here).
+    counted as the kernels issue them.  Dense: every batch of up to G = rows /
+    N configurations runs the 16-row tiles of the workgroup's four waves (448
+    rows in the C = 16 BF16 forms at up to 448 sites, else 512 at C <= 16 and
+    576 at C = 32; the BF16 forms skip a wave's last tile when it starts past
+    the batch's rows), with K padded to whole instruction steps (4 for FP32,
+    32 for BF16: 144 -> 160 at C = 16), plus, for FP32, the 1 -> C lift (K = 9
+    padded to 12; in the BF16 forms the lift runs on the FP32 matrix cores
+    and is not counted here).
     Light cone: the neighbourhood rows padded to 16-row tiles (the FP32 pass
     of the sampled configuration is counted only for the FP32 form).
     Split-BF16 runs three products per output."""
@@ -71,9 +73,20 @@ def eloc_flops(spins, L, C, n, lightcone, conv):
         G = min(rows // N, 64)
         kpad = -(-9 * C // kstep) * kstep
         ntc = -(-C // 16) * 16
-        per_batch = rows * ntc * 2 * n * kpad + (rows * ntc * 2 * 12 if conv == "fp32" else 0)
-        batches = float((-(-(1 + nap.sum(axis=1)) // G)).sum())
-        return f, batches * per_batch * mult
+        tpw = rows // 64
+
+        def tiles(r):  # tiles one batch of r rows runs
+            if conv == "fp32":
+                return 4 * tpw
+            return 4 * (tpw - 1) + sum(1 for w in range(4) if (w + 4 * (tpw - 1)) * 16 < r)
+
+        nconf = 1 + nap.sum(axis=1)
+        nb = -(-nconf // G)
+        last = nconf - G * (nb - 1)
+        t = float((nb - 1).sum()) * tiles(G * N) + sum(float(c) * tiles(int(g) * N)
+                                                        for g, c in zip(*np.unique(last, return_counts=True)))
+        per_tile = 16 * ntc * 2 * (n * kpad + (12 if conv == "fp32" else 0))
+        return f, t * per_tile * mult
     per_row = 2 * 9 * C * C
     alg = np.zeros(4)
     exe = np.zeros(4)

@@ -443,14 +443,24 @@ struct Engine {
   }
 
   // K loop of one C -> C layer over the wave's row tiles with the gather
-  // rows read from the neighbour table; results stay in acc.
+  // rows read from the neighbour table; results stay in acc.  In the BF16
+  // forms a last tile slot that starts at or past row R (a batch shorter
+  // than MAXROWS) is not computed: its acc stays zero and none of its rows
+  // is stored.
   template <bool TR = false>
   __device__ static __forceinline__ void kloop_tab(const char *act, const char *frag, const uint16_t *nbt,
-                                                   f32x4 (&acc)[TPW][NT]) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                   f32x4 (&acc)[TPW][NT], int R = MAXROWS) {
+    const int lane = threadIdx.x & 63;
+    const int wave = F32 ? threadIdx.x >> 6 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int rowi[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) rowi[i] = (wave + i * NW) * 16 + (lane & 15);
+    if constexpr (TPW > 1 && !F32) {
+      if ((wave + (TPW - 1) * NW) * 16 >= R) {
+        kloop_rows<TPW - 1, TR>(act, frag, nbt, rowi, acc);
+        return;
+      }
+    }
     kloop_rows<TPW, TR>(act, frag, nbt, rowi, acc);
   }
 
@@ -695,7 +705,7 @@ struct Engine {
     __syncthreads();
     for (int l = 1; l <= n_layers; ++l) {
       f32x4 acc[TPW][NT];
-      kloop_tab<FWD_TR>(smem_act, smem_frag, nbt, acc);
+      kloop_tab<FWD_TR>(smem_act, smem_frag, nbt, acc, R);
       const float *bias = theta + layer_offset(C, l) + 9 * C * C;
       // FP32: the activation is applied in registers before the barrier, so
       // a wave that finishes its K loop early spends the wait on it and only

@@ -71,6 +71,23 @@ def test_local_energy_flops_dense_and_light_cone_limit():
     assert alg_lc == pytest.approx(s.shape[0] * f + float(nap.sum()) * (f - 2 * L * L * 9 * C), rel=1e-15)
 
 
+def test_local_energy_executed_flops_dense_10x10():
+    # one Neel configuration at 10x10: 200 antiparallel J1 bonds, so 201
+    # configurations.  FP32: 512-row batches of 5 (41 batches, 32 tiles
+    # each, K = 144 plus the lift's 12).  BF16: 448-row batches of 4 (50 of
+    # 400 rows, whose waves 1..3 skip their last tile: 25 tiles; the last
+    # batch of 100 rows skips the last slot of every wave: 24 tiles), K
+    # padded to 160, three products in split BF16
+    s = neel(10, 1)
+    tile = 16 * 16 * 2
+    _, f32 = bench.eloc_flops(s, 10, 16, 6, lightcone=False, conv="fp32")
+    assert f32 == 41 * 32 * tile * (6 * 144 + 12)
+    _, x3 = bench.eloc_flops(s, 10, 16, 6, lightcone=False, conv="bf16x3")
+    assert x3 == (50 * 25 + 24) * tile * 6 * 160 * 3
+    _, b1 = bench.eloc_flops(s, 10, 16, 6, lightcone=False, conv="bf16")
+    assert b1 == x3 / 3
+
+
 def test_sr_stage_roofline_counts():
     # explicit S at 10x10: B P^2 (lower half of S) = 0.812 TFLOP and P^3 / 3
     # = 0.930 TFLOP for the Cholesky, plus the solves
