@@ -80,6 +80,34 @@ def test_local_energy_bf16_forms_10x10(prec, tol):
     _eloc_check(10, 16, 6, prec, uniform_sz0(10, 12, seed=1), th, tol)
 
 
+@pytest.mark.parametrize("L,B", [(12, 6), (14, 4)])
+def test_local_energy_dense_bf16_batch_shapes(L, B):
+    """The dense BF16 forms at C = 16 run 448-row batches.  At 12x12 a batch
+    holds three configurations (432 rows, 27 tiles: three waves run all
+    their tile slots, the fourth skips its empty last one), at 14x14 two
+    (392 rows, 25 tiles; forced to the dense form, which 14x14 does not use
+    by default).  Both against the oracle, per sample and on the mean.  The
+    random-weight energies of a few samples differ in sign and by orders of
+    magnitude, so their mean cancels: its error is taken relative to the mean
+    magnitude.  An empty or misplaced tile would give errors of order one;
+    single BF16 is held to its own (loose) rounding level, which reaches 0.12
+    per sample at 10x10."""
+    C, n = 16, 3
+    th = init_theta(C, n, seed=0)
+    s = uniform_sz0(L, B, seed=5)
+    _, rm = models(L, C, n)
+    ref = R.local_energy(rm, th, s)
+    for prec, tol_each, tol_mean in ((V.PREC_BF16X3, 1e-3, 1e-4), (V.PREC_BF16, 0.5, 5e-2)):
+        gm, _ = models(L, C, n, prec, eloc=V.ELOC_DENSE)
+        announce("dense local_energy batch shape", L, C, n, B, prec)
+        got = host(V.vqmc_local_energy(gm, to_dev(th), to_dev(s)))
+        rel_mean = abs(got.mean() - ref.mean()) / np.abs(ref).mean()
+        rel_each = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+        print("E_loc dense L=%d prec=%d  |dE/N| rel=%.3e  max per-sample rel=%.3e" % (L, prec, rel_mean,
+                                                                                     rel_each.max()))
+        assert rel_mean <= tol_mean and rel_each.max() <= tol_each
+
+
 def test_local_energy_neel_and_edge_configs():
     th = init_theta(8, 2, seed=4)
     s = np.concatenate([neel(6, 1), ferro_like_sz0(6), uniform_sz0(6, 3, seed=9)])
